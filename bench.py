@@ -1,0 +1,198 @@
+"""Throughput of the list-based D3Q19 TRT lattice Boltzmann hot path on one MI355X.
+
+One benchmark "step" is one pass of the whole hot path over the workload:
+assembly of the sparse representation from the flag field (numbering,
+compaction, adjacency), equilibrium initialisation, SWEEPS pull sweeps, and
+the FP64 moments/totals of the final state.  The flag field is resident in
+HBM before the timed region.  value = fluid-lattice updates per second of the
+whole job (MFLUPS, counting fluid cells only).
+
+Default workload: 256^3 tube (diameter 240) packed with radius-12 spheres by
+seeded random sequential addition, periodic in x, force-driven, D3Q19 TRT with
+tau+ = 0.8, magic 3/16, 1000 sweeps, FP64 storage, lexicographic ordering.
+
+Besides the one JSON line the run reports, for the dominant kernel (the
+sweep), the achieved HBM bandwidth from its algorithmic bytes (19 PDFs read +
+19 written + 18 uint32 adjacency entries per fluid cell) and its average
+launch time measured with HIP events on the launch stream, and a CPU baseline:
+the plain FP64 oracle timed on the host cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+METRIC = "MFLUPS and % of HBM peak, D3Q19 TRT sparse sweep; FP64 vs FP32/FP16 at stated error"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_FLUP = {"f64": 376, "f64s": 376, "f32": 224, "f32s": 224, "f16s": 148}
+KERNEL_SOURCES = ["paper_1111_1129_amd/csrc/trt.hip", "paper_1111_1129_amd/csrc/lbm_device.hpp"]
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="tube_packing",
+                    choices=["tube_packing", "small_packing", "large_packing", "channel"])
+    ap.add_argument("--sweeps", type=int, default=1000)
+    ap.add_argument("--order", default="lex")
+    ap.add_argument("--param", type=int, default=0)
+    ap.add_argument("--storage", default="f64", choices=list(BYTES_PER_FLUP))
+    ap.add_argument("--no-nt", action="store_true", help="plain stores instead of nontemporal")
+    ap.add_argument("--no-remap", action="store_true", help="disable the XCD block remap")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target CPU time of the oracle baseline sample (0 = skip)")
+    return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(workload: str, order: str, storage: str):
+    """HBM bytes per sweep launch from the committed PMC summary, if it was
+    taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"trt_{storage}_{workload}_{order}_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_hash = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
+    m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash():
+        return None
+    return float(m_bytes.group(1))
+
+
+def make_workload(name: str):
+    from paper_1111_1129_amd import inputs as I
+    if name == "tube_packing":
+        return I.packing_tube(2), "256^3 tube D=240, RSA spheres r=12, seed 2"
+    if name == "small_packing":
+        return I.packing_small(1), "32^3 box, RSA spheres r=4, seed 1"
+    if name == "large_packing":
+        return I.workload("large_packing"), "512x512x1024 Boolean spheres r~U[8,16], porosity 0.4"
+    if name == "channel":
+        return I.channel(100), "500x100x100 empty channel"
+    raise KeyError(name)
+
+
+def cpu_baseline(geom, order, param, storage, target_s, n_ref):
+    """Oracle sweep timed on the host cores on a bounded number of sweeps."""
+    import oracle as O
+    sp = O.build(geom.flags, geom.periodic, order, param)
+    prm = O.TRT(0.8, 3.0 / 16.0, (1e-6, 0.0, 0.0))
+    f = O.init(sp.n_fluid, shifted=storage.endswith("s"))
+    g = np.empty_like(f)
+    O.step(prm, sp.adj, f, g)  # warm (page-in)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        O.step(prm, sp.adj, f, g)
+        f, g = g, f
+        steps += 1
+        if time.perf_counter() - t0 >= target_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": sp.n_fluid * steps / dt / 1e6, "unit": "MFLUPS", "cores": O.max_threads(),
+            "kind": "oracle",
+            "sample": f"{steps} FP64 sweeps of the same geometry ({sp.n_fluid} fluid cells, "
+                      f"{order}), {dt:.1f} s, OpenMP over cells"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    from paper_1111_1129_amd import _native as N
+    from paper_1111_1129_amd import lattice as L
+
+    N.load()
+    dev = torch.device("cuda:0")
+    geom, desc = make_workload(a.workload)
+    flags = torch.from_numpy(np.ascontiguousarray(geom.flags)).to(dev)
+    prm = L.params(0.8, 3.0 / 16.0, (1e-6, 0.0, 0.0), a.storage, nontemporal=not a.no_nt,
+                   xcd_remap=not a.no_remap)
+    stream = torch.cuda.current_stream()
+
+    def one_pass(ev=None):
+        lat = L.build(flags, geom.periodic, a.order, a.param)
+        st = L.init(lat, prm)
+        if ev is not None:
+            ev[0].record(stream)
+        L.step(st, a.sweeps)
+        if ev is not None:
+            ev[1].record(stream)
+        _, _, totals = L.moments(st, fields=False)
+        return lat, st, totals
+
+    for _ in range(a.warmup):
+        one_pass()
+    torch.cuda.synchronize()
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(a.steps):
+        lat, st, totals = one_pass(events[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    n_fluid = lat.n_fluid
+    sweep_ms = np.mean([e0.elapsed_time(e1) for e0, e1 in events])
+    launch_s = sweep_ms / 1e3 / a.sweeps
+    tot = totals.cpu().numpy()[0]
+    if not np.isfinite(tot).all():
+        print(json.dumps({"error": "non-finite totals", "totals": tot.tolist()}))
+        sys.exit(1)
+
+    flups = n_fluid * a.sweeps * a.steps
+    value = flups / wall / 1e6
+    bpf = BYTES_PER_FLUP[a.storage]
+    achieved = bpf * n_fluid / launch_s / 1e9
+    line = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "MFLUPS",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(wall / a.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": a.storage,
+        "data": "synthetic",
+        "config": {"workload": f"{a.workload}: {desc}", "n_fluid": n_fluid,
+                   "sweeps_per_step": a.sweeps, "order": a.order, "order_param": a.param,
+                   "storage": a.storage, "tau_plus": 0.8, "magic": 0.1875, "force_x": 1e-6,
+                   "nontemporal": not a.no_nt, "xcd_remap": not a.no_remap},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic_from_profile(a.workload, a.order, a.storage),
+                     "kernel": "k_trt (one sweep launch)", "bytes_per_flup": bpf,
+                     "sweep_mflups": round(n_fluid / launch_s / 1e6, 1),
+                     "avg_launch_us": round(launch_s * 1e6, 2)},
+        "cpu_baseline": None,
+    }
+    if a.cpu_seconds > 0:
+        line["cpu_baseline"] = cpu_baseline(geom, a.order, a.param, a.storage, a.cpu_seconds,
+                                            n_fluid)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

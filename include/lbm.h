@@ -1,0 +1,259 @@
+/*
+ * lbm.h -- C ABI of the list-based D3Q19 TRT lattice Boltzmann library for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The method is that of Wittmann, Zeiser, Hager, Wellein, "Domain
+ * decomposition and locality optimization for large-scale lattice Boltzmann
+ * simulations": a sparse representation that stores only fluid cells in a
+ * 1-D list together with an adjacency list (Sec. 2), assembled from a full
+ * flag field through a numbering scheme and a contiguous index (Sec. 3), and
+ * a D3Q19 two-relaxation-time pull sweep over that list (Sec. 1, Sec. 7).
+ *
+ * General conventions
+ *  - Every pointer is a DEVICE pointer unless marked (host).
+ *  - The caller owns all memory.  The library never allocates device memory;
+ *    calls that need scratch space take a caller-provided workspace whose
+ *    size is obtained by calling with workspace == NULL (size query).
+ *  - The library keeps no global state.  Every call is ordered on `stream`
+ *    (a hipStream_t, NULL = the null stream) and asynchronous, except the
+ *    outputs marked "synchronous" which are returned to the host.
+ *  - Every call returns an lbm_status and never aborts or throws.  Argument
+ *    errors are detected on the host before any launch.  A launch failure
+ *    reported by the HIP runtime returns LBM_EHIP; faults that surface later
+ *    are reported by the caller's next synchronisation.
+ *  - Indices: fluid cells are numbered 0..N_f-1 in key order ("contiguous
+ *    index" I_c of Sec. 3, 0-based; solid cells get -1 where the paper writes
+ *    0).  A box cell (x,y,z) of an nx*ny*nz box has linear index
+ *    lin = x + nx*(y + ny*z).
+ *  - PDF arrays are structure-of-arrays [19][stride] (Sec. 7): population i of
+ *    list cell m lives at element i*stride + m.  Several geometries may share
+ *    one set of arrays, each occupying columns [base, base + N_f) ("batched").
+ *
+ * D3Q19 numbering: i = 0 rest; 1,2 = +-x; 3,4 = +-y; 5,6 = +-z;
+ * 7 (1,1,0) 8 (-1,-1,0) 9 (1,-1,0) 10 (-1,1,0) 11 (1,0,1) 12 (-1,0,-1)
+ * 13 (1,0,-1) 14 (-1,0,1) 15 (0,1,1) 16 (0,-1,-1) 17 (0,1,-1) 18 (0,-1,1).
+ * Opposite pairs are (2k-1, 2k).  Weights 1/3, 1/18 (axis), 1/36 (diagonal).
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,     /* bad argument: NULL required pointer, bad dims/enum, stride < n ... */
+    LBM_ECAPACITY = -2,  /* output capacity too small; required size is returned */
+    LBM_EOVERFLOW = -3,  /* index does not fit: 19*stride >= 2^32 or box >= 2^31 cells */
+    LBM_EWORKSPACE = -4, /* workspace missing or smaller than the size query returned */
+    LBM_EHIP = -5,       /* the HIP runtime reported an error */
+    LBM_EBARRIER = -6    /* persistent launch: a grid barrier exceeded its spin limit */
+} lbm_status;
+
+/* Numbering schemes (Sec. 3 "Numbering scheme"; Sec. 7 blocking factor and
+ * Z-curve variants). */
+typedef enum {
+    LBM_ORDER_LEX = 0,     /* key = lin (x fastest) */
+    LBM_ORDER_BLOCKED = 1, /* cubic blocks of edge b = order_param, blocks and the
+                              cells inside a block both lexicographic; edge blocks
+                              truncated; b = 1 is plain lexicographic */
+    LBM_ORDER_MORTON1 = 2, /* Z curve, 1-bit interleave: bit k of x,y,z -> bit 3k,3k+1,3k+2 */
+    LBM_ORDER_MORTON2 = 3, /* Z curve, 2-bit groups: bits [2k,2k+2) of x,y,z -> [6k,6k+2),
+                              [6k+2,6k+4), [6k+4,6k+6) */
+    LBM_ORDER_RANDOM = 4   /* key = 4-round Feistel bijection of lin on [0, 4^h),
+                              4^h >= box (smallest h >= 1); round r maps (L,R) ->
+                              (R, L ^ (splitmix64(seed ^ (r << 32) ^ R) & (2^h - 1)));
+                              seed = order_param.  A control ordering: the paper
+                              allows any injective index function. */
+} lbm_order;
+
+/* PDF storage (the paper stores double precision, Sec. 7).  "Shifted" arrays
+ * hold f_i - w_i.  F64 forms compute in FP64; F32/F16 forms compute in FP32.
+ * Reductions (moments totals) are always accumulated in FP64. */
+typedef enum {
+    LBM_F64 = 0,
+    LBM_F64_SHIFTED = 1,
+    LBM_F32 = 2,
+    LBM_F32_SHIFTED = 3,
+    LBM_F16_SHIFTED = 4
+} lbm_storage;
+
+enum {
+    LBM_FLAG_NONTEMPORAL = 1, /* write the new PDFs with nontemporal stores (Sec. 7) */
+    LBM_FLAG_NO_XCD_REMAP = 2 /* disable the XCD-contiguous block mapping (for study) */
+};
+
+typedef struct {
+    int32_t nx, ny, nz;
+    uint32_t periodic;    /* bit0 x, bit1 y, bit2 z; non-periodic out-of-box = solid */
+    int32_t order;        /* lbm_order */
+    uint32_t order_param; /* blocking factor b (BLOCKED) or seed (RANDOM) */
+} lbm_geom;
+
+/* TRT parameters.  tau_minus = 1/2 + magic / (tau_plus - 1/2); s+- = 1/tau+-.
+ * force = body force G per unit volume (lattice units). */
+typedef struct {
+    double tau_plus;
+    double magic;
+    double force[3];
+    int32_t storage; /* lbm_storage */
+    int32_t flags;   /* LBM_FLAG_* */
+} lbm_params;
+
+/* One geometry of a batch: list columns [base, base + n). */
+typedef struct {
+    int64_t base;
+    int64_t n;
+    int32_t param_index; /* reserved: must be 0 (all segments share params[0]) */
+    int32_t pad;
+} lbm_segment;
+
+/*
+ * lbm_build_adjacency -- assembly of the sparse representation (Sec. 3).
+ *
+ * Numbering scheme -> contiguous index -> adjacency.  Every box cell gets the
+ * key of g->order; fluid cells are ranked by key (I_c, Sec. 3 "Contiguous
+ * index generation": the rank the paper's octree merge of incell runs
+ * computes, here an exclusive prefix count of fluid flags in key order); the
+ * adjacency is found by inspecting each fluid cell's neighbourhood in the full
+ * representation (Sec. 3, last paragraph of the assembly) with bounce-back
+ * encoded implicitly (Sec. 2).  The result is independent of any launch
+ * parameter (Sec. 8: the same geometry and numbering always produce exactly
+ * the same sparse representation).
+ *
+ *  g         (host) box dims, periodicity, ordering.
+ *  flag      uint8 [nz][ny][nx], nonzero = fluid.
+ *  base      first list column of this geometry in the shared arrays.
+ *  stride    row stride of adj (and of the PDF arrays); stride >= base + N_f.
+ *  index_of  int32 [nx*ny*nz] or NULL: I_c of each box cell, -1 for solid.
+ *  cell_of   int32 [cap] or NULL: lin of list cell m (cell_of[m], m < N_f).
+ *            NULL = count-only pass: only *n_fluid is produced.
+ *  adj       uint32 [18][stride] or NULL (compaction only).  Row k is
+ *            direction i = k+1; entry adj[k*stride + base + m] =
+ *              i*stride + base + I_c(x_m - c_i)   if that upstream cell (wrapped
+ *                                                  in periodic directions) is fluid,
+ *              opp(i)*stride + base + m           otherwise (bounce-back).
+ *            The rest population is implicit (slot base + m of row 0).
+ *  cap       capacity of cell_of in cells.
+ *  n_fluid   (host, synchronous) N_f.  Set also when LBM_ECAPACITY is returned.
+ *  workspace device scratch of *ws_bytes bytes; NULL = size query: *ws_bytes
+ *            is set and nothing else happens.
+ *  ws_bytes  (host, in/out) workspace size.
+ * Errors: LBM_EINVAL (NULL g/flag/n_fluid/ws_bytes, dims <= 0, bad order,
+ * b == 0, stride < base + N_f when adj given), LBM_EOVERFLOW (box >= 2^31 cells,
+ * 19*stride >= 2^32), LBM_ECAPACITY (N_f > cap; nothing written), LBM_EWORKSPACE.
+ */
+lbm_status lbm_build_adjacency(const lbm_geom* g, const uint8_t* flag, int64_t base,
+                               int64_t stride, int32_t* index_of, int32_t* cell_of,
+                               uint32_t* adj, int64_t cap, int64_t* n_fluid, void* workspace,
+                               size_t* ws_bytes, void* stream);
+
+/*
+ * lbm_init -- equilibrium initial state.
+ *
+ * Writes f_i = w_i [rho0 + 3 c_i.u0 + 9/2 (c_i.u0)^2 - 3/2 |u0|^2] (minus w_i in
+ * shifted storage, computed as w_i [(rho0 - 1) + ...]) for list cells [0, n)
+ * of every row.  The element type of f follows p->storage.  To initialise a
+ * batch member, offset f by its base (in elements).
+ *  p      (host) parameters (storage is used).
+ *  u0     (host) 3 doubles, or NULL for u0 = 0.
+ * Errors: LBM_EINVAL (NULL p/f, n < 0, stride < n, bad storage).
+ */
+lbm_status lbm_init(const lbm_params* p, int64_t n, int64_t stride, void* f, double rho0,
+                    const double* u0, void* stream);
+
+/*
+ * lbm_step -- n_steps D3Q19 TRT pull sweeps over list cells [0, n)
+ * (Sec. 1, Sec. 2, Sec. 7: TRT on D3Q19, structure of arrays, pull scheme,
+ * indirect addressing, optionally nontemporal stores).
+ *
+ * Per cell m: gather g_0 = f[m], g_i = f[adj[i-1][m]]; rho = sum g;
+ * j = sum c_i g_i; e+_i = w_i (rho + 9/2 (c_i.j)^2 - 3/2 |j|^2); e-_i = 3 w_i c_i.j;
+ * f*_i = g_i - s+ ((g_i + g_opp)/2 - e+_i) - s- ((g_i - g_opp)/2 - e-_i) + 3 w_i c_i.G;
+ * with a solid fraction ns (partial bounce-back): out_i = (1 - ns) f*_i + ns g_opp;
+ * store out_i at element i*stride + m of the destination array.  In shifted
+ * storage the same map acts on f - w with rho read as the density deviation.
+ *
+ *  p, n_params  (host) parameters; n_params must be 1.
+ *  seg, n_seg   (host) batch layout, or NULL/0 for one geometry [0, n).  Segments
+ *               must lie inside [0, n) and not overlap.  They do not change the
+ *               sweep (adjacency entries already carry each member's base).
+ *  adj          uint32 [18][stride] from lbm_build_adjacency.
+ *  ns           double [stride] solid fraction per list cell, or NULL (plain TRT).
+ *  f_a, f_b     two PDF arrays [19][stride] of the storage type.  Step k reads the
+ *               array written by step k-1 (f_a first): the result is in f_b if
+ *               n_steps is odd, in f_a if even.
+ *  persistent   0: one kernel launch per step.  1: a single cooperative launch
+ *               runs all n_steps with a grid-wide barrier between steps; needs
+ *               the workspace (query with workspace == NULL and ws_bytes != NULL).
+ *  workspace, ws_bytes  see above; unused when persistent == 0 (may be NULL/0).
+ * Errors: LBM_EINVAL (NULL p/adj/f_a/f_b, n < 0, stride < n, n_params != 1,
+ * bad storage, tau_plus <= 1/2, bad segments, non-finite parameters),
+ * LBM_EOVERFLOW (19*stride >= 2^32), LBM_EWORKSPACE, LBM_EHIP, LBM_EBARRIER
+ * (persistent only; synchronous check after the launch).
+ */
+lbm_status lbm_step(const lbm_params* p, int32_t n_params, const lbm_segment* seg, int32_t n_seg,
+                    int64_t n, int64_t stride, const uint32_t* adj, const double* ns,
+                    void* f_a, void* f_b, int32_t n_steps, int32_t persistent,
+                    void* workspace, size_t* ws_bytes, void* stream);
+
+/*
+ * lbm_step_adjoint -- transposed Jacobian of one lbm_step (FP64 storage only).
+ *
+ * Forward: f^{t+1} = step(f^t; ns).  Given lam_next = lambda^{t+1} it writes
+ * lambda^t = (d f^{t+1} / d f^t)^T lambda^{t+1} -- the local transposed
+ * collision Jacobian applied per cell and scattered back through the same
+ * adjacency (every slot of lam_t is written exactly once: the pull is a
+ * permutation) -- and accumulates grad_ns[m] += sum_i lambda^{t+1}_i(m)
+ * (g_opp(i) - f*_i), the derivative through the solid fraction.
+ * With lam_next == NULL it writes the seed lambda^T = dJ/df^T of the
+ * objective J = (1/n) sum_m (j_x(m) + G_x/2) (mean x velocity of the state
+ * after the last step, i.e. the mean flux that sets the permeability); then
+ * grad_ns is not touched.
+ *
+ *  f_t      state entering step t ([19][stride], F64 or F64_SHIFTED).
+ *  ns       solid fraction [stride] or NULL (then grad_ns is ignored).
+ *  lam_next double [19][stride] or NULL; lam_t double [19][stride] (output).
+ *  grad_ns  double [stride], accumulated (+=); caller zeroes it.
+ * Errors: LBM_EINVAL (NULL p/adj/f_t/lam_t, n <= 0, stride < n, storage not
+ * FP64), LBM_EOVERFLOW, LBM_EHIP.
+ */
+lbm_status lbm_step_adjoint(const lbm_params* p, int64_t n, int64_t stride, const uint32_t* adj,
+                            const void* f_t, const double* ns, const double* lam_next,
+                            double* lam_t, double* grad_ns, void* stream);
+
+/*
+ * lbm_moments -- macroscopic fields and FP64 totals of a stored state.
+ *
+ * Per list cell, from the populations it gathers through adj (the values the
+ * next sweep would read): rho = sum g (1 + sum h in shifted storage),
+ * u = j + G/2.  Totals per segment: {sum rho, sum u_x, sum u_y, sum u_z},
+ * accumulated in FP64 double-double in a fixed order, so results do not
+ * depend on timing.
+ *
+ *  rho   double [n] or NULL.   u  double [3][n] (rows x, y, z) or NULL.
+ *  seg, n_seg  (host) segments, or NULL/0 for one segment [0, n).
+ *  totals double [4 * max(n_seg,1)] or NULL.
+ *  workspace, ws_bytes  scratch for the reduction (query with workspace NULL);
+ *        not needed when totals == NULL.
+ * Errors: LBM_EINVAL, LBM_EOVERFLOW, LBM_EWORKSPACE, LBM_EHIP.
+ */
+lbm_status lbm_moments(const lbm_params* p, int64_t n, int64_t stride, const uint32_t* adj,
+                       const void* f, double* rho, double* u, const lbm_segment* seg,
+                       int32_t n_seg, double* totals, void* workspace, size_t* ws_bytes,
+                       void* stream);
+
+/* Library version (major*10000 + minor*100 + patch) and a static string for a
+ * status code.  Both are host-only and allocate nothing. */
+int32_t lbm_version(void);
+const char* lbm_status_string(int32_t status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,182 @@
+"""ctypes binding of ``liblbm.so`` (the C ABI declared in include/lbm.h).
+
+Argument marshalling only: every function here forwards to the entry point of
+the same name.  Torch tensors are passed as raw device pointers and the
+current torch stream as the HIP stream.  torch is imported before the library
+is loaded so that the library binds to the same HIP runtime instance as torch.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import torch  # noqa: F401  (loads the HIP runtime the library must share)
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblbm.so")
+
+LBM_OK, LBM_EINVAL, LBM_ECAPACITY, LBM_EOVERFLOW, LBM_EWORKSPACE, LBM_EHIP, LBM_EBARRIER = \
+    0, -1, -2, -3, -4, -5, -6
+ORDERS = {"lex": 0, "blocked": 1, "morton1": 2, "morton2": 3, "random": 4}
+STORAGES = {"f64": 0, "f64s": 1, "f32": 2, "f32s": 3, "f16s": 4}
+STORAGE_DTYPE = {0: torch.float64, 1: torch.float64, 2: torch.float32, 3: torch.float32,
+                 4: torch.float16}
+FLAG_NONTEMPORAL = 1
+FLAG_NO_XCD_REMAP = 2
+
+ENTRY_POINTS = ("lbm_build_adjacency", "lbm_init", "lbm_step", "lbm_step_adjoint",
+                "lbm_moments", "lbm_version", "lbm_status_string")
+
+
+class lbm_geom(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("periodic", C.c_uint32), ("order", C.c_int32), ("order_param", C.c_uint32)]
+
+
+class lbm_params(C.Structure):
+    _fields_ = [("tau_plus", C.c_double), ("magic", C.c_double), ("force", C.c_double * 3),
+                ("storage", C.c_int32), ("flags", C.c_int32)]
+
+
+class lbm_segment(C.Structure):
+    _fields_ = [("base", C.c_int64), ("n", C.c_int64), ("param_index", C.c_int32),
+                ("pad", C.c_int32)]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        self.status = status
+        super().__init__(f"{fn} failed: {status} ({status_string(status)})")
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the library (once).  Raises if it has not been built: there is no
+    fallback implementation."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: build it with "
+                               "`python -m paper_1111_1129_amd.build` (hipcc, gfx950)")
+        lib = C.CDLL(path)
+        P, I32, I64, SZ = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+        lib.lbm_build_adjacency.restype = I32
+        lib.lbm_build_adjacency.argtypes = [C.POINTER(lbm_geom), P, I64, I64, P, P, P, I64,
+                                            C.POINTER(C.c_int64), P, C.POINTER(SZ), P]
+        lib.lbm_init.restype = I32
+        lib.lbm_init.argtypes = [C.POINTER(lbm_params), I64, I64, P, C.c_double, P, P]
+        lib.lbm_step.restype = I32
+        lib.lbm_step.argtypes = [C.POINTER(lbm_params), I32, P, I32, I64, I64, P, P, P, P, I32,
+                                 I32, P, C.POINTER(SZ), P]
+        lib.lbm_step_adjoint.restype = I32
+        lib.lbm_step_adjoint.argtypes = [C.POINTER(lbm_params), I64, I64, P, P, P, P, P, P, P]
+        lib.lbm_moments.restype = I32
+        lib.lbm_moments.argtypes = [C.POINTER(lbm_params), I64, I64, P, P, P, P, P, I32, P, P,
+                                    C.POINTER(SZ), P]
+        lib.lbm_version.restype = I32
+        lib.lbm_version.argtypes = []
+        lib.lbm_status_string.restype = C.c_char_p
+        lib.lbm_status_string.argtypes = [I32]
+        _lib = lib
+        return lib
+
+
+def status_string(status: int) -> str:
+    return load().lbm_status_string(status).decode()
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _check(fn, status):
+    if status != LBM_OK:
+        raise LbmError(fn, status)
+
+
+def make_params(tau_plus=0.8, magic=3.0 / 16.0, force=(0.0, 0.0, 0.0), storage="f64",
+                flags=0) -> lbm_params:
+    st = STORAGES[storage] if isinstance(storage, str) else int(storage)
+    return lbm_params(float(tau_plus), float(magic), (C.c_double * 3)(*map(float, force)),
+                      st, int(flags))
+
+
+def make_segments(segs):
+    if not segs:
+        return None, 0
+    arr = (lbm_segment * len(segs))(*[lbm_segment(int(b), int(n), 0, 0) for b, n in segs])
+    return arr, len(segs)
+
+
+# ---------------------------------------------------------------------------
+# entry points, same names as the C ABI
+# ---------------------------------------------------------------------------
+
+def lbm_build_adjacency(geom: lbm_geom, flag, base, stride, index_of, cell_of, adj, cap,
+                        workspace=None, ws_bytes=None, stream=None, query=False):
+    """Returns (status, n_fluid, ws_bytes).  With query=True only the workspace
+    size is computed."""
+    lib = load()
+    nf = C.c_int64(0)
+    ws = C.c_size_t(0 if ws_bytes is None else ws_bytes)
+    st = lib.lbm_build_adjacency(C.byref(geom), _ptr(flag), base, stride, _ptr(index_of),
+                                 _ptr(cell_of), _ptr(adj), cap, C.byref(nf),
+                                 None if query else _ptr(workspace), C.byref(ws),
+                                 _stream(stream))
+    return st, nf.value, ws.value
+
+
+def lbm_init(params: lbm_params, n, stride, f, rho0=1.0, u0=None, stream=None):
+    lib = load()
+    u = None if u0 is None else (C.c_double * 3)(*map(float, u0))
+    return lib.lbm_init(C.byref(params), n, stride, _ptr(f), float(rho0),
+                        None if u is None else C.cast(u, C.c_void_p), _stream(stream))
+
+
+def lbm_step(params: lbm_params, n, stride, adj, ns, f_a, f_b, n_steps, persistent=0,
+             segments=None, workspace=None, ws_bytes=0, stream=None, query=False):
+    lib = load()
+    seg, n_seg = make_segments(segments)
+    ws = C.c_size_t(ws_bytes)
+    st = lib.lbm_step(C.byref(params), 1, seg, n_seg, n, stride, _ptr(adj), _ptr(ns), _ptr(f_a),
+                      _ptr(f_b), n_steps, persistent, None if query else _ptr(workspace),
+                      C.byref(ws), _stream(stream))
+    return st, ws.value
+
+
+def lbm_step_adjoint(params: lbm_params, n, stride, adj, f_t, ns, lam_next, lam_t, grad_ns,
+                     stream=None):
+    lib = load()
+    return lib.lbm_step_adjoint(C.byref(params), n, stride, _ptr(adj), _ptr(f_t), _ptr(ns),
+                                _ptr(lam_next), _ptr(lam_t), _ptr(grad_ns), _stream(stream))
+
+
+def lbm_moments(params: lbm_params, n, stride, adj, f, rho, u, segments, totals,
+                workspace=None, ws_bytes=0, stream=None, query=False):
+    lib = load()
+    seg, n_seg = make_segments(segments)
+    ws = C.c_size_t(ws_bytes)
+    st = lib.lbm_moments(C.byref(params), n, stride, _ptr(adj), _ptr(f), _ptr(rho), _ptr(u), seg,
+                         n_seg, _ptr(totals), None if query else _ptr(workspace), C.byref(ws),
+                         _stream(stream))
+    return st, ws.value
+
+
+def lbm_version() -> int:
+    return load().lbm_version()

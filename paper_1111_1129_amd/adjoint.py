@@ -1,0 +1,81 @@
+"""Gradient of the mean flux (permeability) with respect to a per-cell
+partial-bounce-back solid fraction, through the hand-written adjoint step.
+
+Forward: T TRT sweeps from rest with solid fraction ns; J = mean over listed
+cells of u_x = j_x + G_x/2 after the last sweep (permeability k = nu J / G_x).
+Backward: two-level checkpointing -- the forward keeps the state every k
+steps; the backward walks the segments in reverse, recomputes the states of
+one segment into a buffer, and applies lbm_step_adjoint from the last state
+of the segment down to its first.  Memory: ceil(T/k) checkpoints + k buffer
+states; work: one extra forward sweep per step.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import _native as N
+from .lattice import Lattice, init, moments, step
+
+
+def forward_states(lat: Lattice, prm, ns: torch.Tensor, T: int, k: int):
+    """Run T steps from rest; return (J, checkpoints at 0, k, 2k, ..., final state)."""
+    st = init(lat, prm, ns=ns)
+    ckpts = []
+    t = 0
+    while t < T:
+        ckpts.append(st.f.clone())
+        n = min(k, T - t)
+        step(st, n)
+        t += n
+    _, _, totals = moments(st, fields=False)
+    J = totals[0, 1] / lat.n_fluid
+    return J, ckpts, st
+
+
+def adjoint_gradient(lat: Lattice, prm, ns: torch.Tensor, T: int, k: int, ckpts=None):
+    """dJ/dns [stride] (float64) by checkpointed reverse sweeps."""
+    if ckpts is None:
+        _, ckpts, _ = forward_states(lat, prm, ns, T, k)
+    S, n = lat.stride, lat.n_fluid
+    dev = lat.device
+    lam = torch.empty((19, S), dtype=torch.float64, device=dev)
+    lam_prev = torch.empty_like(lam)
+    grad = torch.zeros(S, dtype=torch.float64, device=dev)
+    N._check("lbm_step_adjoint", N.lbm_step_adjoint(prm, n, S, lat.adj, None, ns, None, lam, None))
+    buf = [torch.empty_like(ckpts[0]) for _ in range(k)]
+    nseg = len(ckpts)
+    for s in range(nseg - 1, -1, -1):
+        t0 = s * k
+        t1 = min(t0 + k, T)
+        buf[0].copy_(ckpts[s])
+        for j in range(1, t1 - t0):
+            st, _ = N.lbm_step(prm, n, S, lat.adj, ns, buf[j - 1], buf[j], 1)
+            N._check("lbm_step", st)
+        for t in range(t1 - 1, t0 - 1, -1):
+            rc = N.lbm_step_adjoint(prm, n, S, lat.adj, buf[t - t0], ns, lam, lam_prev, grad)
+            N._check("lbm_step_adjoint", rc)
+            lam, lam_prev = lam_prev, lam
+    return grad
+
+
+class PermeabilityFn(torch.autograd.Function):
+    """J = PermeabilityFn.apply(ns, lattice, params, T, k): mean x velocity after
+    T sweeps; backward returns dJ/dns via the adjoint with checkpoints every k."""
+
+    @staticmethod
+    def forward(ctx, ns, lat, prm, T, k):
+        if prm.storage not in (N.STORAGES["f64"], N.STORAGES["f64s"]):
+            raise ValueError("the adjoint needs FP64 storage")
+        nsd = ns.detach().contiguous()
+        J, ckpts, _ = forward_states(lat, prm, nsd, T, k)
+        ctx.lat, ctx.prm, ctx.T, ctx.k = lat, prm, T, k
+        ctx.ckpts = ckpts
+        ctx.save_for_backward(nsd)
+        return J
+
+    @staticmethod
+    def backward(ctx, gJ):
+        (ns,) = ctx.saved_tensors
+        grad = adjoint_gradient(ctx.lat, ctx.prm, ns, ctx.T, ctx.k, ctx.ckpts)
+        ctx.ckpts = None
+        return grad * gJ, None, None, None, None

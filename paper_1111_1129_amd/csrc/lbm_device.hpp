@@ -1,0 +1,166 @@
+// lbm_device.hpp -- device-side building blocks of the gfx950 library:
+// the D3Q19 velocity set, storage traits, the TRT collision of one cell, and
+// launch helpers.  Included by every .hip translation unit of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "lbm.h"
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// D3Q19.  Populations come in opposite pairs (2k-1, 2k), k = 1..9; the odd
+// member's velocity is listed, the even member is its negative.
+// ---------------------------------------------------------------------------
+constexpr int Q = 19;
+constexpr int NPAIR = 9;
+// velocity of the odd member 2k-1 of pair k (index k-1)
+constexpr int PCX[NPAIR] = {1, 0, 0, 1, 1, 1, 1, 0, 0};
+constexpr int PCY[NPAIR] = {0, 1, 0, 1, -1, 0, 0, 1, 1};
+constexpr int PCZ[NPAIR] = {0, 0, 1, 0, 0, 1, -1, 1, -1};
+// 1/18 for the three axis pairs, 1/36 for the six diagonal pairs
+__host__ __device__ constexpr double pair_weight(int k) { return k < 3 ? 1.0 / 18.0 : 1.0 / 36.0; }
+constexpr double W0 = 1.0 / 3.0;
+
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+__host__ __device__ constexpr int vel_x(int i) { return i == 0 ? 0 : ((i & 1) ? PCX[(i - 1) / 2] : -PCX[(i - 1) / 2]); }
+__host__ __device__ constexpr int vel_y(int i) { return i == 0 ? 0 : ((i & 1) ? PCY[(i - 1) / 2] : -PCY[(i - 1) / 2]); }
+__host__ __device__ constexpr int vel_z(int i) { return i == 0 ? 0 : ((i & 1) ? PCZ[(i - 1) / 2] : -PCZ[(i - 1) / 2]); }
+__host__ __device__ constexpr double weight(int i) { return i == 0 ? W0 : pair_weight((i - 1) / 2); }
+
+// ---------------------------------------------------------------------------
+// Storage traits: element type T in memory, arithmetic type A, shift flag.
+// ---------------------------------------------------------------------------
+template <int ST> struct Storage;
+template <> struct Storage<LBM_F64> { using T = double; using A = double; static constexpr bool shifted = false; };
+template <> struct Storage<LBM_F64_SHIFTED> { using T = double; using A = double; static constexpr bool shifted = true; };
+template <> struct Storage<LBM_F32> { using T = float; using A = float; static constexpr bool shifted = false; };
+template <> struct Storage<LBM_F32_SHIFTED> { using T = float; using A = float; static constexpr bool shifted = true; };
+template <> struct Storage<LBM_F16_SHIFTED> { using T = _Float16; using A = float; static constexpr bool shifted = true; };
+
+template <class T, class A> __device__ __forceinline__ A ld(const T* p) { return static_cast<A>(*p); }
+// FP32 -> FP16 conversion rounds to nearest even (IEEE default mode)
+template <class T, class A, bool NT> __device__ __forceinline__ void st(T* p, A v) {
+    if constexpr (NT)
+        __builtin_nontemporal_store(static_cast<T>(v), p);
+    else
+        *p = static_cast<T>(v);
+}
+
+inline size_t storage_bytes(int st) {
+    switch (st) {
+    case LBM_F64: case LBM_F64_SHIFTED: return 8;
+    case LBM_F32: case LBM_F32_SHIFTED: return 4;
+    case LBM_F16_SHIFTED: return 2;
+    default: return 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// TRT constants of one launch (host-computed in FP64).
+// ---------------------------------------------------------------------------
+struct TrtConst {
+    double sp, sm;       // s+ = 1/tau+, s- = 1/tau-
+    double G[3];         // body force
+    double F[NPAIR];     // 3 w c.G for the odd member of each pair
+};
+
+inline TrtConst make_trt_const(const lbm_params& p) {
+    TrtConst c;
+    double tau_minus = 0.5 + p.magic / (p.tau_plus - 0.5);
+    c.sp = 1.0 / p.tau_plus;
+    c.sm = 1.0 / tau_minus;
+    for (int d = 0; d < 3; ++d) c.G[d] = p.force[d];
+    for (int k = 0; k < NPAIR; ++k)
+        c.F[k] = 3.0 * pair_weight(k) * (PCX[k] * p.force[0] + PCY[k] * p.force[1] + PCZ[k] * p.force[2]);
+    return c;
+}
+
+// ---------------------------------------------------------------------------
+// One cell's TRT collision.  g[19] are the gathered populations (pre-collision),
+// in the arithmetic type A.  Writes the post-collision f*[19] into out[] and,
+// if PBB, blends with the bounce-back g_opp.  rho/j are returned for callers
+// that need them (the adjoint).
+// ---------------------------------------------------------------------------
+template <class A>
+struct CellMoments {
+    A rho, jx, jy, jz;
+};
+
+template <class A>
+__device__ __forceinline__ CellMoments<A> cell_moments(const A* g) {
+    CellMoments<A> m;
+    A rho = g[0];
+    A d[NPAIR];
+#pragma unroll
+    for (int k = 0; k < NPAIR; ++k) {
+        rho += g[2 * k + 1] + g[2 * k + 2];
+        d[k] = g[2 * k + 1] - g[2 * k + 2];
+    }
+    m.rho = rho;
+    // j = sum over pairs of c_odd * (g_odd - g_even)
+    m.jx = d[0] + d[3] + d[4] + d[5] + d[6];
+    m.jy = d[1] + d[3] - d[4] + d[7] + d[8];
+    m.jz = d[2] + d[5] - d[6] + d[7] - d[8];
+    return m;
+}
+
+template <class A, bool PBB>
+__device__ __forceinline__ void trt_collide(const A* g, A* out, const TrtConst& c, A ns) {
+    const CellMoments<A> m = cell_moments(g);
+    const A sp = static_cast<A>(c.sp), sm = static_cast<A>(c.sm);
+    const A jj = m.jx * m.jx + m.jy * m.jy + m.jz * m.jz;
+    const A base = m.rho - A(1.5) * jj;  // rho - 3/2 |j|^2
+    // rest population: g+ = g0, g- = 0, e+ = w0 (rho - 3/2 |j|^2)
+    A f0 = g[0] - sp * (g[0] - static_cast<A>(W0) * base);
+    if constexpr (PBB) f0 = (A(1) - ns) * f0 + ns * g[0];
+    out[0] = f0;
+#pragma unroll
+    for (int k = 0; k < NPAIR; ++k) {
+        const int a = 2 * k + 1, b = 2 * k + 2;
+        const A w = static_cast<A>(pair_weight(k));
+        const A cu = A(PCX[k]) * m.jx + A(PCY[k]) * m.jy + A(PCZ[k]) * m.jz;
+        const A ep = w * (base + A(4.5) * cu * cu);
+        const A em = A(3) * w * cu;
+        const A gp = A(0.5) * (g[a] + g[b]);
+        const A gm = A(0.5) * (g[a] - g[b]);
+        const A rp = sp * (gp - ep);
+        const A rm = sm * (gm - em);
+        const A F = static_cast<A>(c.F[k]);
+        A fa = g[a] - rp - rm + F;
+        A fb = g[b] - rp + rm - F;
+        if constexpr (PBB) {
+            fa = (A(1) - ns) * fa + ns * g[b];
+            fb = (A(1) - ns) * fb + ns * g[a];
+        }
+        out[a] = fa;
+        out[b] = fb;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launch geometry.  Workgroups are handed to the 8 XCDs of the MI355X round
+// robin (workgroup w runs on XCD w % 8), and each XCD has its own L2.  The
+// remap below gives XCD x a contiguous eighth of the list so that the cells a
+// workgroup's neighbours read (spatial neighbours are nearby list entries)
+// are in the same L2.
+// ---------------------------------------------------------------------------
+constexpr int NXCD = 8;
+
+__device__ __forceinline__ int64_t logical_block(bool remap) {
+    const int64_t b = blockIdx.x;
+    if (!remap) return b;
+    const int64_t per = gridDim.x / NXCD;  // grid is a multiple of NXCD when remapping
+    return (b % NXCD) * per + b / NXCD;
+}
+
+inline int64_t grid_blocks(int64_t n, int block, bool remap) {
+    int64_t g = (n + block - 1) / block;
+    if (remap) g = (g + NXCD - 1) / NXCD * NXCD;
+    return g < 1 ? 1 : g;
+}
+
+}  // namespace lbm

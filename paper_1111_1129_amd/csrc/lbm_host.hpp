@@ -1,0 +1,62 @@
+// lbm_host.hpp -- host-side helpers shared by the library's entry points:
+// argument validation and HIP error mapping.  Nothing here allocates.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "lbm.h"
+
+namespace lbm {
+
+constexpr int64_t kIndexLimit = int64_t(1) << 32;  // uint32 PDF slot index
+constexpr int64_t kBoxLimit = int64_t(1) << 31;    // int32 box index
+
+#define LBM_TRY_HIP(expr)                              \
+    do {                                               \
+        if ((expr) != hipSuccess) return LBM_EHIP;     \
+    } while (0)
+
+inline lbm_status after_launch() {
+    return hipGetLastError() == hipSuccess ? LBM_OK : LBM_EHIP;
+}
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline bool valid_storage(int st) { return st >= LBM_F64 && st <= LBM_F16_SHIFTED; }
+
+// TRT parameters usable for a sweep: tau+ > 1/2 and tau- > 1/2 (magic > 0),
+// everything finite.
+inline bool valid_params(const lbm_params* p) {
+    if (!p || !valid_storage(p->storage)) return false;
+    if (!std::isfinite(p->tau_plus) || !std::isfinite(p->magic)) return false;
+    if (!(p->tau_plus > 0.5) || !(p->magic > 0.0)) return false;
+    for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(p->force[d])) return false;
+    return true;
+}
+
+// Layout checks common to every call that touches [19][stride] arrays.
+inline lbm_status check_layout(int64_t n, int64_t stride) {
+    if (n < 0 || stride < n || stride < 0) return LBM_EINVAL;
+    if (19 * stride >= kIndexLimit) return LBM_EOVERFLOW;
+    return LBM_OK;
+}
+
+// Segments must be non-empty-or-empty ranges inside [0, n) that do not overlap.
+inline bool valid_segments(const lbm_segment* seg, int32_t n_seg, int64_t n) {
+    if (n_seg < 0 || (n_seg > 0 && !seg)) return false;
+    int64_t prev_end = 0;
+    for (int32_t s = 0; s < n_seg; ++s) {
+        if (seg[s].n < 0 || seg[s].base < prev_end || seg[s].base + seg[s].n > n) return false;
+        if (seg[s].param_index != 0) return false;
+        prev_end = seg[s].base + seg[s].n;
+    }
+    return true;
+}
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace lbm

@@ -1,0 +1,163 @@
+// moments.hip -- macroscopic fields and FP64 totals (lbm_moments).
+//
+// Per cell the gathered populations give rho and u = j + G/2 (always in
+// FP64, whatever the storage).  Totals per segment are reduced in two fixed
+// passes (per-workgroup partials, then one workgroup over the partials) with
+// double-double (TwoSum) accumulation, so they are reproducible bit for bit
+// and accurate to about 1e-30 relative before the final rounding.
+#include <algorithm>
+
+#include "lbm_device.hpp"
+#include "lbm_host.hpp"
+
+namespace lbm {
+
+constexpr int kMomBlock = 256;
+constexpr int kRedThreads = 256;
+
+struct DD {
+    double hi, lo;
+};
+
+// Knuth's TwoSum, then renormalise: (a.hi + a.lo) + (b.hi + b.lo) in DD.
+__device__ __forceinline__ DD dd_add(DD a, DD b) {
+    const double s = a.hi + b.hi;
+    const double bp = s - a.hi;
+    double e = (a.hi - (s - bp)) + (b.hi - bp);
+    e += a.lo + b.lo;
+    const double hi = s + e;
+    return DD{hi, e - (hi - s)};
+}
+
+// Fixed-shape tree reduction of 4 DD values over a workgroup.
+__device__ void block_reduce4(DD v[4], DD (*sh)[4]) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sh[t][q] = v[q];
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if (t < off) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sh[t][q] = dd_add(sh[t][q], sh[t + off][q]);
+        }
+        __syncthreads();
+    }
+}
+
+template <int ST>
+__global__ __launch_bounds__(kMomBlock) void k_moments(const typename Storage<ST>::T* __restrict__ f,
+                                                       const uint32_t* __restrict__ adj, int64_t n0,
+                                                       int64_t cnt, int64_t stride, double gx,
+                                                       double gy, double gz, double* __restrict__ rho,
+                                                       double* __restrict__ u, int64_t ld,
+                                                       double* __restrict__ partial) {
+    using T = typename Storage<ST>::T;
+    __shared__ DD sh[kMomBlock][4];
+    const int64_t local = int64_t(blockIdx.x) * kMomBlock + threadIdx.x;
+    DD v[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+    if (local < cnt) {
+        const int64_t m = n0 + local;
+        double g[Q];
+        g[0] = static_cast<double>(f[m]);
+#pragma unroll
+        for (int k = 0; k < Q - 1; ++k) g[k + 1] = static_cast<double>(f[adj[k * stride + m]]);
+        const CellMoments<double> cm = cell_moments(g);
+        const double r = Storage<ST>::shifted ? 1.0 + cm.rho : cm.rho;
+        const double ux = cm.jx + 0.5 * gx, uy = cm.jy + 0.5 * gy, uz = cm.jz + 0.5 * gz;
+        if (rho) rho[m] = r;
+        if (u) {
+            u[m] = ux;
+            u[ld + m] = uy;
+            u[2 * ld + m] = uz;
+        }
+        v[0].hi = r;
+        v[1].hi = ux;
+        v[2].hi = uy;
+        v[3].hi = uz;
+    }
+    if (!partial) return;
+    block_reduce4(v, sh);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            partial[(int64_t(blockIdx.x) * 4 + q) * 2] = sh[0][q].hi;
+            partial[(int64_t(blockIdx.x) * 4 + q) * 2 + 1] = sh[0][q].lo;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_reduce_partials(const double* __restrict__ partial,
+                                                                 int64_t nblocks,
+                                                                 double* __restrict__ totals) {
+    __shared__ DD sh[kRedThreads][4];
+    DD v[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+    // thread t sums blocks t, t + T, t + 2T, ... in order
+    for (int64_t b = threadIdx.x; b < nblocks; b += kRedThreads) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = dd_add(v[q], DD{partial[(b * 4 + q) * 2], partial[(b * 4 + q) * 2 + 1]});
+    }
+    block_reduce4(v, sh);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) totals[q] = sh[0][q].hi + sh[0][q].lo;
+    }
+}
+
+template <int ST>
+lbm_status launch_moments(const lbm_params& p, int64_t n, int64_t stride, const uint32_t* adj,
+                          const void* f, double* rho, double* u, const lbm_segment* seg,
+                          int32_t n_seg, double* totals, double* partial, hipStream_t s) {
+    lbm_segment whole{0, n, 0, 0};
+    if (!seg || n_seg == 0) {
+        seg = &whole;
+        n_seg = 1;
+    }
+    for (int32_t k = 0; k < n_seg; ++k) {
+        const int64_t cnt = seg[k].n;
+        const int64_t blocks = std::max<int64_t>(1, (cnt + kMomBlock - 1) / kMomBlock);
+        k_moments<ST><<<dim3(unsigned(blocks)), dim3(kMomBlock), 0, s>>>(
+            static_cast<const typename Storage<ST>::T*>(f), adj, seg[k].base, cnt, stride,
+            p.force[0], p.force[1], p.force[2], rho, u, n, totals ? partial : nullptr);
+        if (hipGetLastError() != hipSuccess) return LBM_EHIP;
+        if (totals) {
+            k_reduce_partials<<<1, kRedThreads, 0, s>>>(partial, blocks, totals + 4 * k);
+            if (hipGetLastError() != hipSuccess) return LBM_EHIP;
+        }
+    }
+    return LBM_OK;
+}
+
+}  // namespace lbm
+
+using namespace lbm;
+
+extern "C" lbm_status lbm_moments(const lbm_params* p, int64_t n, int64_t stride,
+                                  const uint32_t* adj, const void* f, double* rho, double* u,
+                                  const lbm_segment* seg, int32_t n_seg, double* totals,
+                                  void* workspace, size_t* ws_bytes, void* stream) {
+    if (!p || !valid_storage(p->storage)) return LBM_EINVAL;
+    if (lbm_status st = check_layout(n, stride); st != LBM_OK) return st;
+    if (!valid_segments(seg, n_seg, n)) return LBM_EINVAL;
+    int64_t largest = (seg && n_seg > 0) ? 0 : n;
+    for (int32_t k = 0; seg && k < n_seg; ++k) largest = std::max(largest, seg[k].n);
+    const size_t need = totals ? align_up(size_t(std::max<int64_t>(1, (largest + kMomBlock - 1) / kMomBlock)) * 8 * sizeof(double), 256) : 0;
+    if (totals && !workspace) {
+        if (!ws_bytes) return LBM_EINVAL;
+        *ws_bytes = need;
+        return LBM_OK;
+    }
+    if (totals && (!ws_bytes || *ws_bytes < need)) return LBM_EWORKSPACE;
+    if (!adj || !f) return LBM_EINVAL;
+    for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(p->force[d])) return LBM_EINVAL;
+    hipStream_t s = as_stream(stream);
+    double* partial = static_cast<double*>(workspace);
+    switch (p->storage) {
+    case LBM_F64: return launch_moments<LBM_F64>(*p, n, stride, adj, f, rho, u, seg, n_seg, totals, partial, s);
+    case LBM_F64_SHIFTED: return launch_moments<LBM_F64_SHIFTED>(*p, n, stride, adj, f, rho, u, seg, n_seg, totals, partial, s);
+    case LBM_F32: return launch_moments<LBM_F32>(*p, n, stride, adj, f, rho, u, seg, n_seg, totals, partial, s);
+    case LBM_F32_SHIFTED: return launch_moments<LBM_F32_SHIFTED>(*p, n, stride, adj, f, rho, u, seg, n_seg, totals, partial, s);
+    case LBM_F16_SHIFTED: return launch_moments<LBM_F16_SHIFTED>(*p, n, stride, adj, f, rho, u, seg, n_seg, totals, partial, s);
+    default: return LBM_EINVAL;
+    }
+}

@@ -1,0 +1,196 @@
+"""Python-level objects over the C ABI: Lattice (sparse representation),
+State (PDF arrays + parameters) and Batch (many geometries in shared arrays).
+
+Every numeric step runs in the HIP library; this module allocates device
+memory with torch and passes pointers and the current stream.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import torch
+
+from . import _native as N
+
+
+@dataclasses.dataclass
+class Lattice:
+    """Sparse representation of one geometry (paper Sec. 2-3)."""
+
+    dims: tuple             # (nx, ny, nz)
+    periodic: int
+    order: str
+    param: int
+    n_fluid: int
+    base: int
+    stride: int
+    index_of: torch.Tensor  # int32 [n_box], -1 = solid
+    cell_of: torch.Tensor   # int32 [n_fluid]
+    adj: torch.Tensor       # int32 storage of uint32 [18][stride]
+
+    @property
+    def device(self):
+        return self.adj.device
+
+
+def _geom(dims, periodic, order, param):
+    nx, ny, nz = dims
+    o = N.ORDERS[order] if isinstance(order, str) else int(order)
+    return N.lbm_geom(int(nx), int(ny), int(nz), int(periodic), o, int(param))
+
+
+def count_fluid(flags: torch.Tensor, periodic=0, order="lex", param=0, stream=None) -> int:
+    """N_f of a flag field (count-only pass of lbm_build_adjacency)."""
+    nz, ny, nx = flags.shape
+    g = _geom((nx, ny, nz), periodic, order, param)
+    idx = torch.empty(nx * ny * nz, dtype=torch.int32, device=flags.device)
+    st, _, ws = N.lbm_build_adjacency(g, flags, 0, 0, idx, None, None, 0, query=True)
+    N._check("lbm_build_adjacency", st)
+    wsb = torch.empty(max(ws, 1), dtype=torch.uint8, device=flags.device)
+    st, nf, _ = N.lbm_build_adjacency(g, flags, 0, 0, idx, None, None, 0, wsb, ws, stream)
+    N._check("lbm_build_adjacency", st)
+    return nf
+
+
+def build(flags: torch.Tensor, periodic: int = 0, order: str = "lex", param: int = 0,
+          base: int = 0, stride: int | None = None, adj: torch.Tensor | None = None,
+          stream=None) -> Lattice:
+    """Assemble the sparse representation of a flag field on the GPU.
+
+    flags: uint8 [nz][ny][nx] on the device, nonzero = fluid.
+    base/stride/adj: place this geometry at columns [base, base + N_f) of an
+    existing [18][stride] adjacency (batched use); by default a new array with
+    stride = N_f is allocated.
+    """
+    assert flags.dtype == torch.uint8 and flags.is_cuda and flags.is_contiguous()
+    nz, ny, nx = flags.shape
+    g = _geom((nx, ny, nz), periodic, order, param)
+    dev = flags.device
+    index_of = torch.empty(nx * ny * nz, dtype=torch.int32, device=dev)
+    st, _, ws = N.lbm_build_adjacency(g, flags, base, 0, index_of, None, None, 0, query=True)
+    N._check("lbm_build_adjacency", st)
+    wsb = torch.empty(max(ws, 1), dtype=torch.uint8, device=dev)
+    st, nf, _ = N.lbm_build_adjacency(g, flags, base, 0, index_of, None, None, 0, wsb, ws, stream)
+    N._check("lbm_build_adjacency", st)
+    if stride is None:
+        stride = base + nf
+    if adj is None:
+        adj = torch.zeros((18, stride), dtype=torch.int32, device=dev)
+    assert adj.shape == (18, stride) and adj.dtype == torch.int32 and adj.is_contiguous()
+    cell_of = torch.empty(max(nf, 1), dtype=torch.int32, device=dev)
+    st, nf2, _ = N.lbm_build_adjacency(g, flags, base, stride, index_of, cell_of, adj, nf, wsb, ws,
+                                       stream)
+    N._check("lbm_build_adjacency", st)
+    assert nf2 == nf
+    return Lattice((nx, ny, nz), periodic, order, param, nf, base, stride, index_of, cell_of[:nf],
+                   adj)
+
+
+@dataclasses.dataclass
+class State:
+    """PDF ping-pong arrays [19][stride] and the TRT parameters."""
+
+    lattice: Lattice
+    params: N.lbm_params
+    f: torch.Tensor                 # current state
+    g: torch.Tensor                 # the other array
+    ns: torch.Tensor | None = None  # float64 [stride] solid fraction (PBB) or None
+    n: int = 0                      # number of listed cells the sweep covers
+    steps: int = 0
+
+    @property
+    def storage(self) -> int:
+        return self.params.storage
+
+
+def params(tau_plus=0.8, magic=3.0 / 16.0, force=(0.0, 0.0, 0.0), storage="f64",
+           nontemporal=False, xcd_remap=True) -> N.lbm_params:
+    flags = (N.FLAG_NONTEMPORAL if nontemporal else 0) | (0 if xcd_remap else N.FLAG_NO_XCD_REMAP)
+    return N.make_params(tau_plus, magic, force, storage, flags)
+
+
+def init(lat: Lattice, prm: N.lbm_params, rho0: float = 1.0, u0=None, ns: torch.Tensor | None = None,
+         n: int | None = None, stream=None) -> State:
+    """Equilibrium state for the listed cells [0, n) (default: base + N_f)."""
+    n = lat.base + lat.n_fluid if n is None else n
+    dt = N.STORAGE_DTYPE[prm.storage]
+    f = torch.empty((19, lat.stride), dtype=dt, device=lat.device)
+    g = torch.empty_like(f)
+    st = N.lbm_init(prm, n, lat.stride, f, rho0, u0, stream)
+    N._check("lbm_init", st)
+    if ns is not None:
+        assert ns.dtype == torch.float64 and ns.numel() >= n and ns.is_contiguous()
+    return State(lat, prm, f, g, ns, n, 0)
+
+
+def set_state(state: State, f: torch.Tensor):
+    """Overwrite the current PDFs (same shape and dtype)."""
+    state.f.copy_(f)
+
+
+def step(state: State, n_steps: int = 1, persistent: bool = False, segments=None, stream=None):
+    """Advance the state by n_steps sweeps (one launch per step, or one
+    persistent cooperative launch)."""
+    lat = state.lattice
+    ws = None
+    wsn = 0
+    if persistent:
+        st, wsn = N.lbm_step(state.params, state.n, lat.stride, lat.adj, state.ns, state.f, state.g,
+                             n_steps, 1, segments, query=True)
+        N._check("lbm_step", st)
+        ws = torch.empty(wsn, dtype=torch.uint8, device=lat.device)
+    st, _ = N.lbm_step(state.params, state.n, lat.stride, lat.adj, state.ns, state.f, state.g,
+                       n_steps, int(persistent), segments, ws, wsn, stream)
+    N._check("lbm_step", st)
+    if n_steps % 2 == 1:
+        state.f, state.g = state.g, state.f
+    state.steps += n_steps
+    return state
+
+
+def moments(state: State, fields: bool = True, segments=None, stream=None):
+    """(rho [n], u [3][n], totals [n_seg or 1][4]) in FP64 on the device."""
+    lat = state.lattice
+    n = state.n
+    dev = lat.device
+    rho = torch.empty(n, dtype=torch.float64, device=dev) if fields else None
+    u = torch.empty((3, n), dtype=torch.float64, device=dev) if fields else None
+    nseg = len(segments) if segments else 1
+    totals = torch.empty((nseg, 4), dtype=torch.float64, device=dev)
+    st, wsn = N.lbm_moments(state.params, n, lat.stride, lat.adj, state.f, rho, u, segments,
+                            totals, query=True)
+    N._check("lbm_moments", st)
+    ws = torch.empty(max(wsn, 1), dtype=torch.uint8, device=dev)
+    st, _ = N.lbm_moments(state.params, n, lat.stride, lat.adj, state.f, rho, u, segments, totals,
+                          ws, wsn, stream)
+    N._check("lbm_moments", st)
+    return rho, u, totals
+
+
+class Batch:
+    """Many geometries in one set of [19][S] / [18][S] arrays.
+
+    Geometry k occupies columns [base_k, base_k + N_k); its adjacency entries
+    carry its base, so one sweep over [0, sum N_k) advances all of them.
+    """
+
+    def __init__(self, flags_list, periodic_list, order="lex", param=0, device="cuda"):
+        counts = []
+        for fl, per in zip(flags_list, periodic_list):
+            counts.append(count_fluid(fl, per, order, param))
+        self.counts = counts
+        self.bases = [sum(counts[:k]) for k in range(len(counts))]
+        self.total = sum(counts)
+        self.stride = self.total
+        self.adj = torch.zeros((18, self.stride), dtype=torch.int32, device=device)
+        self.lattices = []
+        for fl, per, b in zip(flags_list, periodic_list, self.bases):
+            self.lattices.append(build(fl, per, order, param, base=b, stride=self.stride,
+                                       adj=self.adj))
+        self.segments = list(zip(self.bases, self.counts))
+        first = self.lattices[0]
+        self.lattice = Lattice(first.dims, first.periodic, order, param, self.total, 0,
+                               self.stride, first.index_of, first.cell_of, self.adj)
+
+    def init(self, prm, rho0=1.0, u0=None, ns=None):
+        return init(self.lattice, prm, rho0, u0, ns, n=self.total)

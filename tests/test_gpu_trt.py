@@ -1,0 +1,226 @@
+"""GPU TRT sweep, moments and reduced-precision storage vs the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1111_1129_amd import inputs as I
+from paper_1111_1129_amd import lattice as L
+
+from gpu_helpers import W, dev_flags, oracle_params, print_case, random_state, rel_err_f64
+
+pytestmark = pytest.mark.gpu
+
+TOL_F64 = 1e-12  # relative, on unshifted PDF values
+
+
+@pytest.fixture(scope="module")
+def small():
+    g = I.packing_small(1)
+    return g, O.build(g.flags, g.periodic, "lex"), L.build(dev_flags(g), g.periodic, "lex")
+
+
+def run_gpu(lat, prm, f0, steps, ns=None, persistent=False):
+    st = L.init(lat, prm, ns=ns)
+    st.f.copy_(torch.from_numpy(f0))
+    L.step(st, steps, persistent=persistent)
+    return st
+
+
+@pytest.mark.parametrize("storage", ["f64", "f64s"])
+def test_small_packing_100_steps_from_rest(small, storage):
+    g, sp, lat = small
+    shifted = storage == "f64s"
+    prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), storage)
+    print_case("trt", storage, "small_packing", 100)
+    st = L.init(lat, prm)
+    f0 = O.init(sp.n_fluid, shifted=shifted)
+    np.testing.assert_array_equal(st.f.cpu().numpy(), f0)
+    L.step(st, 100)
+    orc = O.run(oracle_params(prm), sp.adj, f0, 100)
+    assert rel_err_f64(st.f.cpu().numpy(), orc, shifted) <= TOL_F64
+
+
+def test_small_packing_random_state_ragged_n(small):
+    g, sp, lat = small
+    assert sp.n_fluid % 256 != 0  # a ragged last workgroup
+    prm = L.params(0.8, 3 / 16, (1e-4, 2e-5, -1e-5), "f64")
+    f0 = random_state(sp.n_fluid, 1)
+    st = run_gpu(lat, prm, f0, 37)
+    orc = O.run(oracle_params(prm), sp.adj, f0, 37)
+    assert rel_err_f64(st.f.cpu().numpy(), orc) <= TOL_F64
+
+
+@pytest.mark.parametrize("order,param", [("blocked", 8), ("morton2", 0), ("random", 5)])
+def test_other_orderings(order, param):
+    g = I.packing_small(1)
+    sp = O.build(g.flags, g.periodic, order, param)
+    lat = L.build(dev_flags(g), g.periodic, order, param)
+    prm = L.params(0.8, 3 / 16, (1e-5, 0, 0), "f64")
+    f0 = random_state(sp.n_fluid, 2)
+    st = run_gpu(lat, prm, f0, 20)
+    orc = O.run(oracle_params(prm), sp.adj, f0, 20)
+    assert rel_err_f64(st.f.cpu().numpy(), orc) <= TOL_F64
+
+
+@pytest.mark.parametrize("n_target", [1, 63, 64, 65, 255, 257, 700])
+def test_tiny_lists(n_target):
+    """Lists shorter than a wave, exactly a wave, just above, and ragged."""
+    rng = np.random.default_rng(n_target)
+    flags = np.zeros((12, 12, 12), dtype=np.uint8)
+    idx = rng.choice(flags.size, n_target, replace=False)
+    flags.ravel()[idx] = 1
+    g = I.Geometry("tiny", flags, 7)
+    sp = O.build(flags, 7, "morton1")
+    lat = L.build(dev_flags(g), 7, "morton1")
+    prm = L.params(0.9, 0.25, (1e-3, -1e-3, 5e-4), "f64")
+    f0 = random_state(sp.n_fluid, 3)
+    st = run_gpu(lat, prm, f0, 5)
+    orc = O.run(oracle_params(prm), sp.adj, f0, 5)
+    assert rel_err_f64(st.f.cpu().numpy(), orc) <= TOL_F64
+
+
+def test_pbb(small):
+    g, sp, lat = small
+    rng = np.random.default_rng(4)
+    ns = rng.uniform(0, 1, sp.n_fluid)
+    prm = L.params(0.8, 3 / 16, (1e-5, 0, 0), "f64s")
+    f0 = random_state(sp.n_fluid, 5, amp=1e-3, shifted=True)
+    st = run_gpu(lat, prm, f0, 25, ns=torch.from_numpy(ns).cuda())
+    orc = O.run(oracle_params(prm), sp.adj, f0, 25, ns=ns)
+    assert rel_err_f64(st.f.cpu().numpy(), orc, shifted=True) <= TOL_F64
+
+
+def test_launch_variants_are_bitwise_identical(small):
+    """Nontemporal stores, the XCD remap and the persistent launch change
+    only where/how cells are processed, not their arithmetic."""
+    g, sp, lat = small
+    f0 = random_state(sp.n_fluid, 6)
+    outs = []
+    for nt, remap, pers in [(False, True, False), (True, True, False), (False, False, False),
+                            (False, True, True), (True, True, True)]:
+        prm = L.params(0.8, 3 / 16, (1e-5, 0, 0), "f64", nontemporal=nt, xcd_remap=remap)
+        outs.append(run_gpu(lat, prm, f0, 9, persistent=pers).f.cpu().numpy())
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o, outs[0])
+
+
+def test_rest_mass_and_uniform_force_on_gpu():
+    g = I.packing_small(1)
+    lat = L.build(dev_flags(g), g.periodic, "lex")
+    st = L.init(lat, L.params(0.8, 3 / 16, (0, 0, 0), "f64s"))
+    L.step(st, 50)
+    assert not st.f.any().item()  # shifted rest state is exactly preserved
+    prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), "f64")
+    st = L.init(lat, prm)
+    m0 = st.f.sum().item()
+    L.step(st, 100)
+    assert abs(st.f.sum().item() - m0) <= 1e-12 * m0
+    # all-fluid periodic box forced from rest: u = (t + 1/2) G
+    box = I.all_fluid(6, 5, 4)
+    latb = L.build(dev_flags(box), 7, "lex")
+    G = (1e-5, -2e-5, 3e-5)
+    stb = L.init(latb, L.params(0.8, 3 / 16, G, "f64s"))
+    L.step(stb, 20)
+    _, u, tot = L.moments(stb)
+    expect = 20.5 * np.array(G)
+    np.testing.assert_allclose(u.cpu().numpy().T, np.tile(expect, (latb.n_fluid, 1)), rtol=1e-13)
+
+
+def test_poiseuille_on_gpu():
+    H = 8
+    g = I.plate_channel(H, nx=3, nz=2)
+    lat = L.build(dev_flags(g), g.periodic, "lex")
+    gx = 1e-6
+    st = L.init(lat, L.params(0.8, 3 / 16, (gx, 0, 0), "f64s"))
+    L.step(st, 16000)
+    _, u, _ = L.moments(st)
+    y = (lat.cell_of.cpu().numpy() // 3) % (H + 2)
+    exact = gx / (2 * 0.1) * (y - 0.5) * (H + 0.5 - y)
+    np.testing.assert_allclose(u[0].cpu().numpy(), exact, rtol=1e-9)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f64s", "f32", "f16s"])
+def test_moments_vs_oracle(small, storage):
+    g, sp, lat = small
+    shifted = storage.endswith("s")
+    prm = L.params(0.8, 3 / 16, (1e-5, 2e-6, 0), storage)
+    f0 = random_state(sp.n_fluid, 7, amp=1e-2, shifted=shifted)
+    dt = {"f64": np.float64, "f64s": np.float64, "f32": np.float32, "f16s": np.float16}[storage]
+    f0 = f0.astype(dt)
+    st = L.init(lat, prm)
+    st.f.copy_(torch.from_numpy(f0))
+    rho, u, tot = L.moments(st)
+    orho, ou, otot = O.moments(oracle_params(prm), sp.adj, f0.astype(np.float64), shifted)
+    np.testing.assert_allclose(rho.cpu().numpy(), orho, rtol=1e-14, atol=0)
+    np.testing.assert_allclose(u.cpu().numpy(), ou, rtol=0, atol=1e-16)
+    t = tot.cpu().numpy()[0]
+    np.testing.assert_allclose(t[0], otot[0], rtol=1e-15)
+    np.testing.assert_allclose(t[1:], otot[1:], rtol=0, atol=1e-15 * np.abs(ou).sum())
+
+
+def test_moments_segments_and_determinism(small):
+    g, sp, lat = small
+    prm = L.params(0.8, 3 / 16, (1e-5, 0, 0), "f64")
+    st = run_gpu(lat, prm, random_state(sp.n_fluid, 8), 3)
+    n = sp.n_fluid
+    segs = [(0, 1000), (1000, 1), (1001, n - 1001)]
+    _, _, t1 = L.moments(st, segments=segs)
+    _, _, t2 = L.moments(st, segments=segs)
+    assert torch.equal(t1, t2)
+    f = st.f.cpu().numpy()
+    for k, (b, c) in enumerate(segs):
+        _, _, ot = O.moments(oracle_params(prm), sp.adj, f, False, b, b + c)
+        np.testing.assert_allclose(t1[k].cpu().numpy(), ot, rtol=1e-13, atol=1e-18)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f32s", "f16s"])
+def test_reduced_precision_one_step(small, storage):
+    """One step from a stored FP32/FP16 state: the GPU computes in FP32, the
+    oracle in FP64 on the same widened inputs and rounds to the storage type.
+    Bound: one storage ulp of the result (the rounding decision may differ)
+    plus the FP32 evaluation error, 64 eps32 of the largest value involved."""
+    g, sp, lat = small
+    shifted = storage.endswith("s")
+    prm = L.params(0.8, 3 / 16, (1e-5, 0, 0), storage)
+    f0 = random_state(sp.n_fluid, 9, amp=2e-2, shifted=shifted)
+    dt = np.float16 if storage == "f16s" else np.float32
+    f0 = f0.astype(dt)
+    st = L.init(lat, prm)
+    st.f.copy_(torch.from_numpy(f0))
+    L.step(st, 1)
+    gpu = st.f.cpu().numpy().astype(np.float64)
+    exact = O.run(oracle_params(prm), sp.adj, f0.astype(np.float64), 1)
+    orc = O.round_storage(exact, storage)
+    scale = np.abs(f0.astype(np.float64)).max() if shifted else 1.0
+    ulp = np.spacing(np.abs(exact).astype(dt)).astype(np.float64)
+    tol = ulp + 64 * np.finfo(np.float32).eps * scale
+    assert (np.abs(gpu - orc) <= tol).all()
+    # and the result is not trivially the input
+    assert np.abs(gpu - f0.astype(np.float64)).max() > 10 * tol.max()
+
+
+def test_full_size_tube_sampled_step():
+    """The full 256^3 tube in the benchmark's launch configuration: after 20
+    GPU steps from a random state, one more GPU step is compared on sampled
+    cell ranges (head, middle, ragged tail) with the oracle's step of the same
+    input state."""
+    g = I.packing_tube(2)
+    lat = L.build(dev_flags(g), g.periodic, "lex")
+    n = lat.n_fluid
+    adj = lat.adj.cpu().numpy().view(np.uint32)
+    prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), "f64", nontemporal=True)
+    print_case("tube full size", n)
+    st = L.init(lat, prm)
+    st.f.copy_(torch.from_numpy(random_state(n, 10)))
+    L.step(st, 20)
+    f_t = st.f.cpu().numpy()
+    L.step(st, 1)
+    f_next = st.f.cpu().numpy()
+    orc = np.zeros_like(f_t)
+    ranges = [(0, 4096), (n // 3, n // 3 + 3000), (n // 2 + 17, n // 2 + 5000), (n - 2049, n)]
+    for a, b in ranges:
+        O.step(oracle_params(prm), adj, f_t, orc, n0=a, n1=b)
+        assert rel_err_f64(f_next[:, a:b], orc[:, a:b]) <= TOL_F64
+    # and the whole state conserves mass
+    assert abs(f_next.sum() - f_t.sum()) <= 1e-12 * f_t.sum()
