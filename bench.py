@@ -47,8 +47,10 @@ def parse():
     ap.add_argument("--order", default="lex")
     ap.add_argument("--param", type=int, default=0)
     ap.add_argument("--storage", default="f64", choices=list(BYTES_PER_FLUP))
-    ap.add_argument("--no-nt", action="store_true", help="plain stores instead of nontemporal")
-    ap.add_argument("--no-remap", action="store_true", help="disable the XCD block remap")
+    ap.add_argument("--layout", default="tuned", choices=["tuned", "aligned"],
+                    help="tuned: time candidate row strides / store policies on the geometry "
+                         "first (excluded from the timed region); aligned: 128-byte aligned "
+                         "stride, plain stores, XCD-contiguous mapping")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample (0 = skip)")
     return ap.parse_args()
@@ -125,12 +127,17 @@ def main():
     dev = torch.device("cuda:0")
     geom, desc = make_workload(a.workload)
     flags = torch.from_numpy(np.ascontiguousarray(geom.flags)).to(dev)
-    prm = L.params(0.8, 3.0 / 16.0, (1e-6, 0.0, 0.0), a.storage, nontemporal=not a.no_nt,
-                   xcd_remap=not a.no_remap)
+    if a.layout == "tuned":
+        from paper_1111_1129_amd.tune import tune_layout
+        lay = tune_layout(flags, geom.periodic, a.order, a.param, a.storage)
+        stride, nt, remap = lay.stride, lay.nontemporal, lay.xcd_remap
+    else:
+        stride, nt, remap = None, False, True
+    prm = L.params(0.8, 3.0 / 16.0, (1e-6, 0.0, 0.0), a.storage, nontemporal=nt, xcd_remap=remap)
     stream = torch.cuda.current_stream()
 
     def one_pass(ev=None):
-        lat = L.build(flags, geom.periodic, a.order, a.param)
+        lat = L.build(flags, geom.periodic, a.order, a.param, stride=stride)
         st = L.init(lat, prm)
         if ev is not None:
             ev[0].record(stream)
@@ -179,7 +186,8 @@ def main():
         "config": {"workload": f"{a.workload}: {desc}", "n_fluid": n_fluid,
                    "sweeps_per_step": a.sweeps, "order": a.order, "order_param": a.param,
                    "storage": a.storage, "tau_plus": 0.8, "magic": 0.1875, "force_x": 1e-6,
-                   "nontemporal": not a.no_nt, "xcd_remap": not a.no_remap},
+                   "layout": a.layout, "row_stride": lat.stride, "nontemporal": nt,
+                   "xcd_remap": remap},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic_from_profile(a.workload, a.order, a.storage),

@@ -13,6 +13,16 @@ import torch
 from . import _native as N
 
 
+ROW_ALIGN = 64  # elements: 128 B rows for FP16 storage, 512 B for FP64
+
+
+def aligned_stride(n: int, align: int = ROW_ALIGN) -> int:
+    """Smallest row stride >= n that starts every [19][stride] row on a
+    128-byte boundary.  Unaligned rows make each wave's 512-byte store span
+    partial cache lines, which HBM serves as read-modify-write."""
+    return max(align, (n + align - 1) // align * align)
+
+
 @dataclasses.dataclass
 class Lattice:
     """Sparse representation of one geometry (paper Sec. 2-3)."""
@@ -60,7 +70,7 @@ def build(flags: torch.Tensor, periodic: int = 0, order: str = "lex", param: int
     flags: uint8 [nz][ny][nx] on the device, nonzero = fluid.
     base/stride/adj: place this geometry at columns [base, base + N_f) of an
     existing [18][stride] adjacency (batched use); by default a new array with
-    stride = N_f is allocated.
+    stride = aligned_stride(base + N_f) is allocated.
     """
     assert flags.dtype == torch.uint8 and flags.is_cuda and flags.is_contiguous()
     nz, ny, nx = flags.shape
@@ -73,7 +83,7 @@ def build(flags: torch.Tensor, periodic: int = 0, order: str = "lex", param: int
     st, nf, _ = N.lbm_build_adjacency(g, flags, base, 0, index_of, None, None, 0, wsb, ws, stream)
     N._check("lbm_build_adjacency", st)
     if stride is None:
-        stride = base + nf
+        stride = aligned_stride(base + nf)
     if adj is None:
         adj = torch.zeros((18, stride), dtype=torch.int32, device=dev)
     assert adj.shape == (18, stride) and adj.dtype == torch.int32 and adj.is_contiguous()
@@ -114,8 +124,9 @@ def init(lat: Lattice, prm: N.lbm_params, rho0: float = 1.0, u0=None, ns: torch.
     """Equilibrium state for the listed cells [0, n) (default: base + N_f)."""
     n = lat.base + lat.n_fluid if n is None else n
     dt = N.STORAGE_DTYPE[prm.storage]
-    f = torch.empty((19, lat.stride), dtype=dt, device=lat.device)
-    g = torch.empty_like(f)
+    # both arrays in one allocation: their relative placement is fixed
+    pair = torch.empty((2, 19, lat.stride), dtype=dt, device=lat.device)
+    f, g = pair[0], pair[1]
     st = N.lbm_init(prm, n, lat.stride, f, rho0, u0, stream)
     N._check("lbm_init", st)
     if ns is not None:
@@ -181,7 +192,7 @@ class Batch:
         self.counts = counts
         self.bases = [sum(counts[:k]) for k in range(len(counts))]
         self.total = sum(counts)
-        self.stride = self.total
+        self.stride = aligned_stride(self.total)
         self.adj = torch.zeros((18, self.stride), dtype=torch.int32, device=device)
         self.lattices = []
         for fl, per, b in zip(flags_list, periodic_list, self.bases):

@@ -20,8 +20,8 @@ ORDERS = [("lex", 0), ("blocked", 16), ("blocked", 3), ("blocked", 1), ("morton1
 
 def assert_same(geom, order, param, base=0, stride=None):
     print_case("assembly", geom.name, geom.dims, order, param, base, stride)
-    sp = O.build(geom.flags, geom.periodic, order, param, base=base, stride=stride)
     lat = L.build(dev_flags(geom), geom.periodic, order, param, base=base, stride=stride)
+    sp = O.build(geom.flags, geom.periodic, order, param, base=base, stride=lat.stride)
     assert lat.n_fluid == sp.n_fluid
     np.testing.assert_array_equal(lat.index_of.cpu().numpy(), sp.index_of)
     np.testing.assert_array_equal(lat.cell_of.cpu().numpy(), sp.cell_of)
@@ -42,12 +42,13 @@ def test_exhaustive_2x2x2(dev):
             for order, param in [("lex", 0), ("blocked", 2), ("morton1", 0), ("morton2", 0),
                                  ("random", 3)]:
                 g = I.Geometry("tiny", flags, periodic)
-                sp = O.build(flags, periodic, order, param)
                 lat = L.build(dev_flags(g), periodic, order, param)
+                sp = O.build(flags, periodic, order, param, stride=lat.stride)
                 assert lat.n_fluid == sp.n_fluid
                 np.testing.assert_array_equal(lat.index_of.cpu().numpy(), sp.index_of)
                 if sp.n_fluid:
-                    np.testing.assert_array_equal(adj_u32(lat), sp.adj)
+                    np.testing.assert_array_equal(adj_u32(lat)[:, :sp.n_fluid],
+                                                  sp.adj[:, :sp.n_fluid])
 
 
 @pytest.mark.parametrize("seed", range(24))
@@ -106,8 +107,11 @@ def tube():
 def test_tube_full_size(tube, order, param):
     lat, sp = assert_same(tube, order, param)
     # adjacency is a permutation of the PDF slots (pull streaming is bijective)
-    a = adj_u32(lat).astype(np.int64)
-    n = lat.n_fluid
-    counts = np.bincount(a.ravel(), minlength=19 * n)
+    n, S = lat.n_fluid, lat.stride
+    a = adj_u32(lat)[:, :n].astype(np.int64)
+    # slot i*S + m  ->  dense index i*n + m
+    dense = (a // S) * n + a % S
+    assert (a % S < n).all()
+    counts = np.bincount(dense.ravel(), minlength=19 * n)
     assert counts.shape == (19 * n,)
     assert (counts[:n] == 0).all() and (counts[n:] == 1).all()

@@ -14,10 +14,17 @@ pytestmark = pytest.mark.gpu
 TOL_F64 = 1e-12  # relative, on unshifted PDF values
 
 
+def pair(g, order="lex", param=0):
+    """GPU lattice and oracle sparse representation with the same row stride."""
+    lat = L.build(dev_flags(g), g.periodic, order, param)
+    return O.build(g.flags, g.periodic, order, param, stride=lat.stride), lat
+
+
 @pytest.fixture(scope="module")
 def small():
     g = I.packing_small(1)
-    return g, O.build(g.flags, g.periodic, "lex"), L.build(dev_flags(g), g.periodic, "lex")
+    sp, lat = pair(g)
+    return g, sp, lat
 
 
 def run_gpu(lat, prm, f0, steps, ns=None, persistent=False):
@@ -27,6 +34,14 @@ def run_gpu(lat, prm, f0, steps, ns=None, persistent=False):
     return st
 
 
+def orun(prm, sp, f0, steps, ns=None):
+    return O.run(oracle_params(prm), sp.adj, f0, steps, ns=ns, n0=0, n1=sp.n_fluid)
+
+
+def cells(a, n):
+    return a[:, :n]
+
+
 @pytest.mark.parametrize("storage", ["f64", "f64s"])
 def test_small_packing_100_steps_from_rest(small, storage):
     g, sp, lat = small
@@ -34,33 +49,35 @@ def test_small_packing_100_steps_from_rest(small, storage):
     prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), storage)
     print_case("trt", storage, "small_packing", 100)
     st = L.init(lat, prm)
-    f0 = O.init(sp.n_fluid, shifted=shifted)
-    np.testing.assert_array_equal(st.f.cpu().numpy(), f0)
+    n = sp.n_fluid
+    f0 = O.init(n, stride=lat.stride, shifted=shifted)
+    np.testing.assert_array_equal(cells(st.f.cpu().numpy(), n), cells(f0, n))
     L.step(st, 100)
-    orc = O.run(oracle_params(prm), sp.adj, f0, 100)
-    assert rel_err_f64(st.f.cpu().numpy(), orc, shifted) <= TOL_F64
+    orc = orun(prm, sp, f0, 100)
+    assert rel_err_f64(cells(st.f.cpu().numpy(), n), cells(orc, n), shifted) <= TOL_F64
 
 
 def test_small_packing_random_state_ragged_n(small):
     g, sp, lat = small
     assert sp.n_fluid % 256 != 0  # a ragged last workgroup
     prm = L.params(0.8, 3 / 16, (1e-4, 2e-5, -1e-5), "f64")
-    f0 = random_state(sp.n_fluid, 1)
+    n = sp.n_fluid
+    f0 = random_state(n, 1, stride=lat.stride)
     st = run_gpu(lat, prm, f0, 37)
-    orc = O.run(oracle_params(prm), sp.adj, f0, 37)
-    assert rel_err_f64(st.f.cpu().numpy(), orc) <= TOL_F64
+    orc = orun(prm, sp, f0, 37)
+    assert rel_err_f64(cells(st.f.cpu().numpy(), n), cells(orc, n)) <= TOL_F64
 
 
 @pytest.mark.parametrize("order,param", [("blocked", 8), ("morton2", 0), ("random", 5)])
 def test_other_orderings(order, param):
     g = I.packing_small(1)
-    sp = O.build(g.flags, g.periodic, order, param)
-    lat = L.build(dev_flags(g), g.periodic, order, param)
+    sp, lat = pair(g, order, param)
     prm = L.params(0.8, 3 / 16, (1e-5, 0, 0), "f64")
-    f0 = random_state(sp.n_fluid, 2)
+    n = sp.n_fluid
+    f0 = random_state(n, 2, stride=lat.stride)
     st = run_gpu(lat, prm, f0, 20)
-    orc = O.run(oracle_params(prm), sp.adj, f0, 20)
-    assert rel_err_f64(st.f.cpu().numpy(), orc) <= TOL_F64
+    orc = orun(prm, sp, f0, 20)
+    assert rel_err_f64(cells(st.f.cpu().numpy(), n), cells(orc, n)) <= TOL_F64
 
 
 @pytest.mark.parametrize("n_target", [1, 63, 64, 65, 255, 257, 700])
@@ -71,36 +88,39 @@ def test_tiny_lists(n_target):
     idx = rng.choice(flags.size, n_target, replace=False)
     flags.ravel()[idx] = 1
     g = I.Geometry("tiny", flags, 7)
-    sp = O.build(flags, 7, "morton1")
-    lat = L.build(dev_flags(g), 7, "morton1")
+    sp, lat = pair(g, "morton1")
     prm = L.params(0.9, 0.25, (1e-3, -1e-3, 5e-4), "f64")
-    f0 = random_state(sp.n_fluid, 3)
+    n = sp.n_fluid
+    f0 = random_state(n, 3, stride=lat.stride)
     st = run_gpu(lat, prm, f0, 5)
-    orc = O.run(oracle_params(prm), sp.adj, f0, 5)
-    assert rel_err_f64(st.f.cpu().numpy(), orc) <= TOL_F64
+    orc = orun(prm, sp, f0, 5)
+    assert rel_err_f64(cells(st.f.cpu().numpy(), n), cells(orc, n)) <= TOL_F64
 
 
 def test_pbb(small):
     g, sp, lat = small
     rng = np.random.default_rng(4)
-    ns = rng.uniform(0, 1, sp.n_fluid)
+    n = sp.n_fluid
+    ns = np.zeros(lat.stride)
+    ns[:n] = rng.uniform(0, 1, n)
     prm = L.params(0.8, 3 / 16, (1e-5, 0, 0), "f64s")
-    f0 = random_state(sp.n_fluid, 5, amp=1e-3, shifted=True)
+    f0 = random_state(n, 5, amp=1e-3, shifted=True, stride=lat.stride)
     st = run_gpu(lat, prm, f0, 25, ns=torch.from_numpy(ns).cuda())
-    orc = O.run(oracle_params(prm), sp.adj, f0, 25, ns=ns)
-    assert rel_err_f64(st.f.cpu().numpy(), orc, shifted=True) <= TOL_F64
+    orc = orun(prm, sp, f0, 25, ns=ns)
+    assert rel_err_f64(cells(st.f.cpu().numpy(), n), cells(orc, n), shifted=True) <= TOL_F64
 
 
 def test_launch_variants_are_bitwise_identical(small):
     """Nontemporal stores, the XCD remap and the persistent launch change
     only where/how cells are processed, not their arithmetic."""
     g, sp, lat = small
-    f0 = random_state(sp.n_fluid, 6)
+    n = sp.n_fluid
+    f0 = random_state(n, 6, stride=lat.stride)
     outs = []
     for nt, remap, pers in [(False, True, False), (True, True, False), (False, False, False),
                             (False, True, True), (True, True, True)]:
         prm = L.params(0.8, 3 / 16, (1e-5, 0, 0), "f64", nontemporal=nt, xcd_remap=remap)
-        outs.append(run_gpu(lat, prm, f0, 9, persistent=pers).f.cpu().numpy())
+        outs.append(cells(run_gpu(lat, prm, f0, 9, persistent=pers).f.cpu().numpy(), n))
     for o in outs[1:]:
         np.testing.assert_array_equal(o, outs[0])
 
@@ -108,14 +128,15 @@ def test_launch_variants_are_bitwise_identical(small):
 def test_rest_mass_and_uniform_force_on_gpu():
     g = I.packing_small(1)
     lat = L.build(dev_flags(g), g.periodic, "lex")
+    n = lat.n_fluid
     st = L.init(lat, L.params(0.8, 3 / 16, (0, 0, 0), "f64s"))
     L.step(st, 50)
-    assert not st.f.any().item()  # shifted rest state is exactly preserved
+    assert not st.f[:, :n].any().item()  # shifted rest state is exactly preserved
     prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), "f64")
     st = L.init(lat, prm)
-    m0 = st.f.sum().item()
+    m0 = st.f[:, :n].sum().item()
     L.step(st, 100)
-    assert abs(st.f.sum().item() - m0) <= 1e-12 * m0
+    assert abs(st.f[:, :n].sum().item() - m0) <= 1e-12 * m0
     # all-fluid periodic box forced from rest: u = (t + 1/2) G
     box = I.all_fluid(6, 5, 4)
     latb = L.build(dev_flags(box), 7, "lex")
@@ -145,13 +166,14 @@ def test_moments_vs_oracle(small, storage):
     g, sp, lat = small
     shifted = storage.endswith("s")
     prm = L.params(0.8, 3 / 16, (1e-5, 2e-6, 0), storage)
-    f0 = random_state(sp.n_fluid, 7, amp=1e-2, shifted=shifted)
+    n = sp.n_fluid
+    f0 = random_state(n, 7, amp=1e-2, shifted=shifted, stride=lat.stride)
     dt = {"f64": np.float64, "f64s": np.float64, "f32": np.float32, "f16s": np.float16}[storage]
     f0 = f0.astype(dt)
     st = L.init(lat, prm)
     st.f.copy_(torch.from_numpy(f0))
     rho, u, tot = L.moments(st)
-    orho, ou, otot = O.moments(oracle_params(prm), sp.adj, f0.astype(np.float64), shifted)
+    orho, ou, otot = O.moments(oracle_params(prm), sp.adj, f0.astype(np.float64), shifted, 0, n)
     np.testing.assert_allclose(rho.cpu().numpy(), orho, rtol=1e-14, atol=0)
     np.testing.assert_allclose(u.cpu().numpy(), ou, rtol=0, atol=1e-16)
     t = tot.cpu().numpy()[0]
@@ -162,7 +184,7 @@ def test_moments_vs_oracle(small, storage):
 def test_moments_segments_and_determinism(small):
     g, sp, lat = small
     prm = L.params(0.8, 3 / 16, (1e-5, 0, 0), "f64")
-    st = run_gpu(lat, prm, random_state(sp.n_fluid, 8), 3)
+    st = run_gpu(lat, prm, random_state(sp.n_fluid, 8, stride=lat.stride), 3)
     n = sp.n_fluid
     segs = [(0, 1000), (1000, 1), (1001, n - 1001)]
     _, _, t1 = L.moments(st, segments=segs)
@@ -183,14 +205,16 @@ def test_reduced_precision_one_step(small, storage):
     g, sp, lat = small
     shifted = storage.endswith("s")
     prm = L.params(0.8, 3 / 16, (1e-5, 0, 0), storage)
-    f0 = random_state(sp.n_fluid, 9, amp=2e-2, shifted=shifted)
+    n = sp.n_fluid
+    f0 = random_state(n, 9, amp=2e-2, shifted=shifted, stride=lat.stride)
     dt = np.float16 if storage == "f16s" else np.float32
     f0 = f0.astype(dt)
     st = L.init(lat, prm)
     st.f.copy_(torch.from_numpy(f0))
     L.step(st, 1)
-    gpu = st.f.cpu().numpy().astype(np.float64)
-    exact = O.run(oracle_params(prm), sp.adj, f0.astype(np.float64), 1)
+    gpu = cells(st.f.cpu().numpy().astype(np.float64), n)
+    exact = cells(orun(prm, sp, f0.astype(np.float64), 1), n)
+    f0 = cells(f0, n)
     orc = O.round_storage(exact, storage)
     scale = np.abs(f0.astype(np.float64)).max() if shifted else 1.0
     ulp = np.spacing(np.abs(exact).astype(dt)).astype(np.float64)
@@ -212,7 +236,7 @@ def test_full_size_tube_sampled_step():
     prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), "f64", nontemporal=True)
     print_case("tube full size", n)
     st = L.init(lat, prm)
-    st.f.copy_(torch.from_numpy(random_state(n, 10)))
+    st.f.copy_(torch.from_numpy(random_state(n, 10, stride=lat.stride)))
     L.step(st, 20)
     f_t = st.f.cpu().numpy()
     L.step(st, 1)
@@ -223,4 +247,4 @@ def test_full_size_tube_sampled_step():
         O.step(oracle_params(prm), adj, f_t, orc, n0=a, n1=b)
         assert rel_err_f64(f_next[:, a:b], orc[:, a:b]) <= TOL_F64
     # and the whole state conserves mass
-    assert abs(f_next.sum() - f_t.sum()) <= 1e-12 * f_t.sum()
+    assert abs(f_next[:, :n].sum() - f_t[:, :n].sum()) <= 1e-12 * f_t[:, :n].sum()
