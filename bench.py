@@ -47,10 +47,14 @@ def parse():
     ap.add_argument("--order", default="lex")
     ap.add_argument("--param", type=int, default=0)
     ap.add_argument("--storage", default="f64", choices=list(BYTES_PER_FLUP))
-    ap.add_argument("--layout", default="tuned", choices=["tuned", "aligned"],
+    ap.add_argument("--layout", default="tuned", choices=["tuned", "aligned", "given"],
                     help="tuned: time candidate row strides / store policies on the geometry "
                          "first (excluded from the timed region); aligned: 128-byte aligned "
-                         "stride, plain stores, XCD-contiguous mapping")
+                         "stride, plain stores, contiguous eighth per XCD; given: --stride/--nt/--chunk")
+    ap.add_argument("--stride", type=int, default=0, help="row stride for --layout given")
+    ap.add_argument("--nt", type=int, default=1, help="nontemporal stores for --layout given")
+    ap.add_argument("--chunk", type=int, default=0,
+                    help="consecutive tiles per XCD for --layout given (0 = one eighth each)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample (0 = skip)")
     return ap.parse_args()
@@ -130,10 +134,14 @@ def main():
     if a.layout == "tuned":
         from paper_1111_1129_amd.tune import tune_layout
         lay = tune_layout(flags, geom.periodic, a.order, a.param, a.storage)
-        stride, nt, remap = lay.stride, lay.nontemporal, lay.xcd_remap
+        stride, nt, chunk = lay.stride, lay.nontemporal, lay.xcd_chunk
+        for row in lay.table:
+            print("tune stride=%d nt=%d chunk=%d: %.0f MFLUPS" % row, file=sys.stderr)
+    elif a.layout == "given":
+        stride, nt, chunk = (a.stride or None), bool(a.nt), a.chunk
     else:
-        stride, nt, remap = None, False, True
-    prm = L.params(0.8, 3.0 / 16.0, (1e-6, 0.0, 0.0), a.storage, nontemporal=nt, xcd_remap=remap)
+        stride, nt, chunk = None, False, 0
+    prm = L.params(0.8, 3.0 / 16.0, (1e-6, 0.0, 0.0), a.storage, nontemporal=nt, xcd_chunk=chunk)
     stream = torch.cuda.current_stream()
 
     def one_pass(ev=None):
@@ -187,7 +195,7 @@ def main():
                    "sweeps_per_step": a.sweeps, "order": a.order, "order_param": a.param,
                    "storage": a.storage, "tau_plus": 0.8, "magic": 0.1875, "force_x": 1e-6,
                    "layout": a.layout, "row_stride": lat.stride, "nontemporal": nt,
-                   "xcd_remap": remap},
+                   "xcd_chunk": chunk},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic_from_profile(a.workload, a.order, a.storage),

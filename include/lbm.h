@@ -84,7 +84,13 @@ typedef enum {
 
 enum {
     LBM_FLAG_NONTEMPORAL = 1, /* write the new PDFs with nontemporal stores (Sec. 7) */
-    LBM_FLAG_NO_XCD_REMAP = 2 /* disable the XCD-contiguous block mapping (for study) */
+    /* Workgroup-to-XCD mapping of the sweep, bits [8, 16) of flags, a power of
+     * two k: the hardware hands workgroup w to XCD w % 8; the sweep relabels
+     * workgroups so that each XCD takes k consecutive list tiles before the
+     * next XCD's k.  k = 1 keeps the hardware round robin; 0 (default) gives
+     * each XCD one contiguous eighth of the list.  Results do not depend on it. */
+    LBM_FLAG_XCD_CHUNK_SHIFT = 8,
+    LBM_FLAG_XCD_CHUNK_MASK = 0xff00
 };
 
 typedef struct {

@@ -23,7 +23,7 @@ STORAGES = {"f64": 0, "f64s": 1, "f32": 2, "f32s": 3, "f16s": 4}
 STORAGE_DTYPE = {0: torch.float64, 1: torch.float64, 2: torch.float32, 3: torch.float32,
                  4: torch.float16}
 FLAG_NONTEMPORAL = 1
-FLAG_NO_XCD_REMAP = 2
+FLAG_XCD_CHUNK_SHIFT = 8
 
 ENTRY_POINTS = ("lbm_build_adjacency", "lbm_init", "lbm_step", "lbm_step_adjoint",
                 "lbm_moments", "lbm_version", "lbm_status_string")

@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "lbm.h"
@@ -142,25 +143,71 @@ __device__ __forceinline__ void trt_collide(const A* g, A* out, const TrtConst& 
 }
 
 // ---------------------------------------------------------------------------
+// One cell update of the pull sweep: gather the 18 upstream populations
+// through adj (plus the own rest population), collide, store the 19 results
+// to the cell's own column of the destination rows.
+// ---------------------------------------------------------------------------
+template <int ST, bool PBB, bool NT>
+__device__ __forceinline__ void update_cell(const typename Storage<ST>::T* __restrict__ src,
+                                            typename Storage<ST>::T* __restrict__ dst,
+                                            const uint32_t* __restrict__ adj,
+                                            const double* __restrict__ ns, int64_t m,
+                                            int64_t stride, const TrtConst& c) {
+    using T = typename Storage<ST>::T;
+    using A = typename Storage<ST>::A;
+    uint32_t a[Q - 1];
+    const uint32_t* ap = adj + m;
+#pragma unroll
+    for (int k = 0; k < Q - 1; ++k) a[k] = ap[k * stride];
+    A g[Q];
+    g[0] = ld<T, A>(src + m);
+#pragma unroll
+    for (int k = 0; k < Q - 1; ++k) g[k + 1] = ld<T, A>(src + a[k]);
+    A s = A(0);
+    if constexpr (PBB) s = static_cast<A>(ns[m]);
+    A out[Q];
+    trt_collide<A, PBB>(g, out, c, s);
+    T* dp = dst + m;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) st<T, A, NT>(dp + i * stride, out[i]);
+}
+
+// ---------------------------------------------------------------------------
 // Launch geometry.  Workgroups are handed to the 8 XCDs of the MI355X round
-// robin (workgroup w runs on XCD w % 8), and each XCD has its own L2.  The
-// remap below gives XCD x a contiguous eighth of the list so that the cells a
-// workgroup's neighbours read (spatial neighbours are nearby list entries)
-// are in the same L2.
+// robin (workgroup w runs on XCD w % 8; checked on the device through the
+// XCC_ID hardware register), and each XCD has its own L2.  The sweep relabels
+// workgroups so that each XCD takes `chunk` consecutive list tiles at a time:
+// the gathers of neighbouring tiles share cache lines at tile edges, which
+// then stay in one L2, while all XCDs still sweep nearby parts of the list
+// (DRAM page locality).  chunk = grid/8 gives each XCD one contiguous eighth;
+// chunk = 1 is the hardware order.
 // ---------------------------------------------------------------------------
 constexpr int NXCD = 8;
 
-__device__ __forceinline__ int64_t logical_block(bool remap) {
+// chunk_shift = log2(chunk); the grid is a multiple of NXCD << chunk_shift.
+__device__ __forceinline__ int64_t logical_block(int chunk_shift) {
     const int64_t b = blockIdx.x;
-    if (!remap) return b;
-    const int64_t per = gridDim.x / NXCD;  // grid is a multiple of NXCD when remapping
-    return (b % NXCD) * per + b / NXCD;
+    const int64_t super = b >> (3 + chunk_shift);        // group of NXCD * chunk workgroups
+    const int64_t xcd = b & (NXCD - 1);
+    const int64_t within = (b >> 3) & ((int64_t(1) << chunk_shift) - 1);
+    return (super << (3 + chunk_shift)) + (xcd << chunk_shift) + within;
 }
 
-inline int64_t grid_blocks(int64_t n, int block, bool remap) {
-    int64_t g = (n + block - 1) / block;
-    if (remap) g = (g + NXCD - 1) / NXCD * NXCD;
-    return g < 1 ? 1 : g;
+// Grid for n cells in blocks of `block`, padded to a multiple of NXCD << shift.
+inline int64_t grid_blocks(int64_t n, int block, int chunk_shift) {
+    const int64_t g = (n + block - 1) / block;
+    const int64_t q = int64_t(NXCD) << chunk_shift;
+    return std::max<int64_t>(q, (g + q - 1) / q * q);
+}
+
+// log2 of the XCD chunk for n cells from the LBM_FLAG_XCD_CHUNK bits.
+inline int chunk_shift_for(int32_t flags, int64_t n, int block) {
+    const int64_t k = (flags & LBM_FLAG_XCD_CHUNK_MASK) >> LBM_FLAG_XCD_CHUNK_SHIFT;
+    int64_t chunk = k;
+    if (k == 0) chunk = ((n + block - 1) / block + NXCD - 1) / NXCD;  // one eighth each
+    int s = 0;
+    while ((int64_t(1) << (s + 1)) <= chunk && s < 24) ++s;  // largest power of two <= chunk
+    return s;
 }
 
 }  // namespace lbm

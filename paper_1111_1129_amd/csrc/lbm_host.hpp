@@ -31,6 +31,10 @@ inline bool valid_storage(int st) { return st >= LBM_F64 && st <= LBM_F16_SHIFTE
 // everything finite.
 inline bool valid_params(const lbm_params* p) {
     if (!p || !valid_storage(p->storage)) return false;
+    const int32_t known = LBM_FLAG_NONTEMPORAL | LBM_FLAG_XCD_CHUNK_MASK;
+    if (p->flags & ~known) return false;
+    const int32_t chunk = (p->flags & LBM_FLAG_XCD_CHUNK_MASK) >> LBM_FLAG_XCD_CHUNK_SHIFT;
+    if (chunk & (chunk - 1)) return false;  // a power of two (or 0)
     if (!std::isfinite(p->tau_plus) || !std::isfinite(p->magic)) return false;
     if (!(p->tau_plus > 0.5) || !(p->magic > 0.0)) return false;
     for (int d = 0; d < 3; ++d)

@@ -114,8 +114,11 @@ class State:
 
 
 def params(tau_plus=0.8, magic=3.0 / 16.0, force=(0.0, 0.0, 0.0), storage="f64",
-           nontemporal=False, xcd_remap=True) -> N.lbm_params:
-    flags = (N.FLAG_NONTEMPORAL if nontemporal else 0) | (0 if xcd_remap else N.FLAG_NO_XCD_REMAP)
+           nontemporal=False, xcd_chunk=0) -> N.lbm_params:
+    """TRT parameters.  xcd_chunk: consecutive list tiles per XCD (a power of
+    two; 1 = hardware round robin, 0 = one contiguous eighth per XCD)."""
+    assert xcd_chunk >= 0 and xcd_chunk & (xcd_chunk - 1) == 0 and xcd_chunk < 256
+    flags = (N.FLAG_NONTEMPORAL if nontemporal else 0) | (xcd_chunk << N.FLAG_XCD_CHUNK_SHIFT)
     return N.make_params(tau_plus, magic, force, storage, flags)
 
 

@@ -6,8 +6,8 @@ sweep's sustained HBM bandwidth also depends on where the 19 + 19 PDF rows
 and the 18 adjacency rows fall in the HBM channel interleave (set by the row
 stride) and on the store policy, so those are tuned the same way: a handful
 of candidate strides (all 128-byte aligned) x {plain, nontemporal stores} x
-{XCD-contiguous, round-robin workgroup mapping} are each timed over a few
-sweeps, and the fastest is kept.  Results do not depend on the choice (the
+a few workgroup-to-XCD chunk lengths are each timed over a few sweeps, and
+the fastest is kept.  Results do not depend on the choice (the
 arithmetic per cell is identical); only the speed does.
 """
 from __future__ import annotations
@@ -23,7 +23,7 @@ from . import lattice as L
 class Layout:
     stride: int
     nontemporal: bool
-    xcd_remap: bool
+    xcd_chunk: int
     mflups: float = 0.0
     table: list = dataclasses.field(default_factory=list)
 
@@ -44,7 +44,8 @@ def candidate_strides(n: int) -> list[int]:
 
 def tune_layout(flags: torch.Tensor, periodic: int, order: str = "lex", param: int = 0,
                 storage: str = "f64", force=(1e-6, 0.0, 0.0), sweeps: int = 6,
-                candidates: list[int] | None = None, max_bytes: int | None = None) -> Layout:
+                candidates: list[int] | None = None,
+                chunks: tuple = (1, 4, 16, 64, 0)) -> Layout:
     """Time the candidate layouts on this geometry and return the fastest."""
     n = L.count_fluid(flags, periodic, order, param)
     cands = candidates or candidate_strides(n)
@@ -54,8 +55,8 @@ def tune_layout(flags: torch.Tensor, periodic: int, order: str = "lex", param: i
     for S in cands:
         lat = L.build(flags, periodic, order, param, stride=S)
         for nt in (False, True):
-            for remap in (True, False):
-                prm = L.params(0.8, 3.0 / 16.0, force, storage, nontemporal=nt, xcd_remap=remap)
+            for chunk in chunks:
+                prm = L.params(0.8, 3.0 / 16.0, force, storage, nontemporal=nt, xcd_chunk=chunk)
                 st = L.init(lat, prm)
                 L.step(st, 2)
                 e0 = torch.cuda.Event(enable_timing=True)
@@ -66,9 +67,9 @@ def tune_layout(flags: torch.Tensor, periodic: int, order: str = "lex", param: i
                 e1.synchronize()
                 t = e0.elapsed_time(e1) / 1e3 / sweeps
                 mflups = n / t / 1e6
-                table.append((S, nt, remap, round(mflups, 1)))
+                table.append((S, nt, chunk, round(mflups, 1)))
                 if best is None or mflups > best.mflups:
-                    best = Layout(S, nt, remap, mflups)
+                    best = Layout(S, nt, chunk, mflups)
                 del st
         del lat
     best.table = table

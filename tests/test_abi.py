@@ -97,6 +97,8 @@ def test_host_side_argument_errors(lib):
     assert step(N.make_params(0.8, 0.0)) == N.LBM_EINVAL             # tau- = 1/2
     assert step(N.make_params(0.8, 3 / 16, (float("nan"), 0, 0))) == N.LBM_EINVAL
     assert step(N.make_params(0.8, 3 / 16, storage=9)) == N.LBM_EINVAL
+    assert step(N.make_params(0.8, 3 / 16, flags=3 << 8)) == N.LBM_EINVAL  # chunk not 2^k
+    assert step(N.make_params(0.8, 3 / 16, flags=1 << 20)) == N.LBM_EINVAL  # unknown flag bit
     assert step(good, n=10, stride=5) == N.LBM_EINVAL                # stride < n
     assert step(good, n_params=2) == N.LBM_EINVAL
     assert step(good, a=dummy, b=dummy) == N.LBM_EINVAL              # in-place not allowed

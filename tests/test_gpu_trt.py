@@ -111,15 +111,15 @@ def test_pbb(small):
 
 
 def test_launch_variants_are_bitwise_identical(small):
-    """Nontemporal stores, the XCD remap and the persistent launch change
+    """Nontemporal stores, the XCD chunk mapping and the persistent launch change
     only where/how cells are processed, not their arithmetic."""
     g, sp, lat = small
     n = sp.n_fluid
     f0 = random_state(n, 6, stride=lat.stride)
     outs = []
-    for nt, remap, pers in [(False, True, False), (True, True, False), (False, False, False),
-                            (False, True, True), (True, True, True)]:
-        prm = L.params(0.8, 3 / 16, (1e-5, 0, 0), "f64", nontemporal=nt, xcd_remap=remap)
+    for nt, chunk, pers in [(False, 0, False), (True, 0, False), (False, 1, False), (True, 4, False),
+                            (False, 2, False), (False, 0, True), (True, 0, True)]:
+        prm = L.params(0.8, 3 / 16, (1e-5, 0, 0), "f64", nontemporal=nt, xcd_chunk=chunk)
         outs.append(cells(run_gpu(lat, prm, f0, 9, persistent=pers).f.cpu().numpy(), n))
     for o in outs[1:]:
         np.testing.assert_array_equal(o, outs[0])
