@@ -11,6 +11,14 @@ Default workload: 256^3 tube (diameter 240) packed with radius-12 spheres by
 seeded random sequential addition, periodic in x, force-driven, D3Q19 TRT with
 tau+ = 0.8, magic 3/16, 1000 sweeps, FP64 storage, lexicographic ordering.
 
+Experiments (``--experiment``, one JSON line per configuration, see
+bench_experiments.py): precision (FP64 / FP32 / shifted FP16 storage on the
+512x512x1024 packing, speed-up and velocity error), adjoint (gradient of the
+mean flux w.r.t. a partial-bounce-back field, checked against central
+differences), batched (64 uneven geometries, one persistent launch vs one
+launch per step vs separate launches), orderings (lexicographic, blocking
+factors, Z curves, random on the tube).
+
 Besides the one JSON line the run reports, for the dominant kernel (the
 sweep), the achieved HBM bandwidth from its algorithmic bytes (19 PDFs read +
 19 written + 18 uint32 adjacency entries per fluid cell) and its average
@@ -55,6 +63,12 @@ def parse():
     ap.add_argument("--nt", type=int, default=1, help="nontemporal stores for --layout given")
     ap.add_argument("--chunk", type=int, default=0,
                     help="consecutive tiles per XCD for --layout given (0 = one eighth each)")
+    ap.add_argument("--experiment", default="headline",
+                    choices=["headline", "precision", "adjoint", "batched", "orderings"],
+                    help="headline: the JSON line below; the others print one JSON line per "
+                         "configuration (see the module docstring)")
+    ap.add_argument("--scale", type=int, default=1,
+                    help="experiments: divide workload edge lengths by this (quick checks)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample (0 = skip)")
     return ap.parse_args()
@@ -128,6 +142,10 @@ def main():
     from paper_1111_1129_amd import lattice as L
 
     N.load()
+    if a.experiment != "headline":
+        import bench_experiments
+        getattr(bench_experiments, a.experiment)(a)
+        return
     dev = torch.device("cuda:0")
     geom, desc = make_workload(a.workload)
     flags = torch.from_numpy(np.ascontiguousarray(geom.flags)).to(dev)

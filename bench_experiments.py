@@ -1,0 +1,252 @@
+"""Measurement experiments of bench.py (``python bench.py --experiment NAME``).
+
+Each prints one JSON line per configuration.  All inputs are the seeded
+synthetic workloads of paper_1111_1129_amd.inputs; every timed number is the
+average duration of the kernels measured with HIP events on the launch
+stream.
+"""
+from __future__ import annotations
+
+import json
+import time
+
+import numpy as np
+import torch
+
+from paper_1111_1129_amd import _native as N
+from paper_1111_1129_amd import adjoint as AD
+from paper_1111_1129_amd import inputs as I
+from paper_1111_1129_amd import lattice as L
+from paper_1111_1129_amd.tune import tune_layout, candidate_strides
+
+BYTES = {"f64": 376, "f64s": 376, "f32": 224, "f32s": 224, "f16s": 148}
+PEAK = 8000.0
+
+
+def emit(d):
+    print(json.dumps(d), flush=True)
+
+
+def timed(fn):
+    """Seconds for fn() on the current stream (HIP events)."""
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    out = fn()
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / 1e3, out
+
+
+def quick_layout(flags, periodic, order, param, storage, force=(1e-6, 0.0, 0.0)):
+    n = L.count_fluid(flags, periodic, order, param)
+    cands = sorted({L.aligned_stride(n), candidate_strides(n)[-3]})
+    return tune_layout(flags, periodic, order, param, storage, force, sweeps=4,
+                       candidates=cands, chunks=(1, 0))
+
+
+def dev_flags(g):
+    return torch.from_numpy(np.ascontiguousarray(g.flags)).cuda()
+
+
+# ---------------------------------------------------------------------------
+def precision(a):
+    """FP64 vs FP32 / shifted storage: speed and velocity error against FP64."""
+    g = I.workload("large_packing", scale=a.scale)
+    flags = dev_flags(g)
+    sweeps = 500
+    forms = ["f64", "f64s", "f32", "f32s", "f16s"]
+    layouts = {st: quick_layout(flags, g.periodic, "lex", 0, st) for st in forms}
+    for gx in (1e-6, 1e-5, 1e-4):
+        ref = None
+        t_ref = None
+        for st in forms:
+            lay = layouts[st]
+            lat = L.build(flags, g.periodic, "lex", stride=lay.stride)
+            prm = L.params(0.8, 3 / 16, (gx, 0, 0), st, nontemporal=lay.nontemporal,
+                           xcd_chunk=lay.xcd_chunk)
+            state = L.init(lat, prm)
+            L.step(state, 2)
+            state = L.init(lat, prm)
+            t, _ = timed(lambda: L.step(state, sweeps))
+            _, u, tot = L.moments(state)
+            n = lat.n_fluid
+            rec = {"experiment": "precision", "workload": f"large_packing/{a.scale}",
+                   "n_fluid": n, "sweeps": sweeps, "storage": st, "gx": gx,
+                   "mflups": round(n * sweeps / t / 1e6, 1),
+                   "gbs": round(BYTES[st] * n * sweeps / t / 1e9, 1),
+                   "hbm_frac": round(BYTES[st] * n * sweeps / t / 1e9 / PEAK, 4),
+                   "stride": lat.stride, "nt": lay.nontemporal, "chunk": lay.xcd_chunk,
+                   "mass": float(tot[0, 0]), "mean_ux": float(tot[0, 1]) / n}
+            if st == "f64":
+                ref, t_ref = u.clone(), t
+            else:
+                d = u - ref
+                rec["speedup_vs_f64"] = round(t_ref / t, 3)
+                rec["u_rel_l2"] = float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(ref))
+                rec["u_rel_max"] = float(d.abs().max() / ref.abs().max())
+                rec["ux_mean_rel"] = float((u[0].mean() - ref[0].mean()) / ref[0].mean())
+            emit(rec)
+            del lat, state, u
+            torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------------------
+def adjoint(a):
+    """Gradient of the mean flux w.r.t. the PBB solid fraction: adjoint with
+    two-level checkpointing vs central finite differences on 32 cells."""
+    n_edge = 128 // a.scale
+    g = I.pbb_box(4, n=n_edge)
+    flags = dev_flags(g)
+    lat = L.build(flags, g.periodic, "lex")
+    n, S = lat.n_fluid, lat.stride
+    cell = lat.cell_of.cpu().numpy()
+    ns_host = np.zeros(S)
+    ns_host[:n] = g.ns.ravel()[cell]
+    ns = torch.from_numpy(ns_host).cuda()
+    prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), "f64s")
+    T, k = 500, 22
+    t_fwd, (J, ckpts, _) = timed(lambda: AD.forward_states(lat, prm, ns, T, k))
+    t_bwd, grad = timed(lambda: AD.adjoint_gradient(lat, prm, ns, T, k, ckpts))
+    grad = grad.cpu().numpy()[:n]
+    # adjoint kernel alone
+    lam = torch.zeros((19, S), dtype=torch.float64, device="cuda")
+    lam2 = torch.empty_like(lam)
+    gr = torch.zeros(S, dtype=torch.float64, device="cuda")
+    N.lbm_step_adjoint(prm, n, S, lat.adj, ckpts[0], ns, lam, lam2, gr)
+    t_adj, _ = timed(lambda: [N.lbm_step_adjoint(prm, n, S, lat.adj, ckpts[0], ns, lam, lam2, gr)
+                              for _ in range(20)])
+    t_adj /= 20
+    del ckpts
+    torch.cuda.empty_cache()
+
+    def ux_of(nsv):
+        st = L.init(lat, prm, ns=nsv)
+        L.step(st, T)
+        _, u, _ = L.moments(st)
+        return u[0]
+
+    def dJ(e):
+        # J(ns + e) - J(ns - e) from the per-cell velocity difference: the
+        # two runs' x velocities are subtracted cell by cell before summing,
+        # so the difference is not quantised at one ulp of J as a difference
+        # of two rounded means would be.
+        return float((ux_of(ns + e) - ux_of(ns - e)).sum()) / n
+
+    rng = np.random.default_rng(44)
+    inner = np.flatnonzero((ns_host[:n] > 0.05) & (ns_host[:n] < 0.95))
+    cells = rng.choice(inner, 32, replace=False)
+    hs = (1e-2, 1e-3, 1e-4, 1e-5)
+    fds = {h: [] for h in hs}
+    t0 = time.perf_counter()
+    for c in cells:
+        for h in hs:
+            e = torch.zeros(S, dtype=torch.float64, device="cuda")
+            e[int(c)] = h
+            fds[h].append(dJ(e) / (2 * h))
+    t_fd = time.perf_counter() - t0
+    g32 = grad[cells]
+    per_h = {h: np.abs(g32 - np.array(v)) / np.abs(np.array(v)) for h, v in fds.items()}
+    # Richardson: central differences have an h^2 leading error, so
+    # (4 D(h/10) - ...) -- here the classic 2-point combination of h and h/10
+    rich = (100 * np.array(fds[1e-3]) - np.array(fds[1e-2])) / 99
+    per_h["richardson_1e-2_1e-3"] = np.abs(g32 - rich) / np.abs(rich)
+    errs = per_h[1e-4]
+    emit({"experiment": "adjoint", "workload": f"pbb_box {n_edge}^3", "n_fluid": n, "steps": T,
+          "checkpoint_every": k, "J_mean_ux": float(J), "forward_s": round(t_fwd, 4),
+          "backward_s": round(t_bwd, 4), "backward_over_forward": round(t_bwd / t_fwd, 2),
+          "adjoint_step_us": round(t_adj * 1e6, 1),
+          "adjoint_gbs": round(552 * n / t_adj / 1e9, 1),
+          "adjoint_hbm_frac": round(552 * n / t_adj / 1e9 / PEAK, 4),
+          "fd_cells": 32, "fd_h": 1e-4, "fd_rel_err_max": float(errs.max()),
+          "fd_rel_err_median": float(np.median(errs)), "fd_pass_1e-6": int((errs <= 1e-6).sum()),
+          "fd_by_h": {str(h): {"max": float(v.max()), "median": float(np.median(v)),
+                               "pass_1e-6": int((v <= 1e-6).sum())} for h, v in per_h.items()},
+          "grad_abs_median": float(np.median(np.abs(g32))), "fd_seconds": round(t_fd, 1),
+          "cells": [{"cell": int(c), "ns": float(ns_host[c]), "adjoint": float(g32[i]),
+                     **{f"fd_{h:g}": float(fds[h][i]) for h in hs}} for i, c in enumerate(cells)]})
+
+
+# ---------------------------------------------------------------------------
+def batched(a):
+    """64 uneven geometries: one persistent launch vs one launch per step over
+    the concatenated list vs separate per-geometry launches."""
+    count = max(1, 64 // a.scale)
+    geoms = I.batch_packings(count=count)
+    flags = [dev_flags(g) for g in geoms]
+    steps = 200
+    for storage in ("f32", "f32s"):
+        batch = L.Batch(flags, [g.periodic for g in geoms], "lex")
+        prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), storage)
+        tot_n = batch.total
+        st = batch.init(prm)
+        L.step(st, 2)
+        st = batch.init(prm)
+        t_step, _ = timed(lambda: L.step(st, steps))
+        f_step = st.f[:, :tot_n].clone()
+        stp = batch.init(prm)
+        t_pers, _ = timed(lambda: L.step(stp, steps, persistent=True, segments=batch.segments))
+        same = bool(torch.equal(stp.f[:, :tot_n], f_step))
+        solos = []
+        for fl, g in zip(flags, geoms):
+            lat = L.build(fl, g.periodic, "lex")
+            solos.append(L.init(lat, prm))
+
+        def separate():
+            for _ in range(steps):
+                for s_ in solos:
+                    L.step(s_, 1)
+
+        t_sep, _ = timed(separate)
+        _, _, tot = L.moments(st, fields=False, segments=batch.segments)
+        emit({"experiment": "batched", "geometries": count, "n_fluid_total": tot_n,
+              "edge_min": min(g.dims[0] for g in geoms), "edge_max": max(g.dims[0] for g in geoms),
+              "storage": storage, "steps": steps,
+              "mflups_persistent": round(tot_n * steps / t_pers / 1e6, 1),
+              "mflups_launch_per_step": round(tot_n * steps / t_step / 1e6, 1),
+              "mflups_separate_launches": round(tot_n * steps / t_sep / 1e6, 1),
+              "persistent_equals_per_step": same,
+              "gbs_persistent": round(BYTES[storage] * tot_n * steps / t_pers / 1e9, 1),
+              "gbs_launch_per_step": round(BYTES[storage] * tot_n * steps / t_step / 1e9, 1),
+              "mass_finite": bool(torch.isfinite(tot).all())})
+        del batch, st, stp, solos
+        torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------------------
+def orderings(a):
+    """Sweep and assembly speed vs cell ordering (the paper's Fig. 4 study on
+    one GPU): lexicographic, blocking factors, Z curves, random."""
+    g, desc = (I.packing_tube(2), "tube_packing") if a.workload == "tube_packing" else \
+        (I.channel(100), "channel")
+    flags = dev_flags(g)
+    sweeps = 200
+    cases = [("lex", 0)] + [("blocked", b) for b in (2, 4, 8, 16, 32, 64, 100)] + \
+        [("morton1", 0), ("morton2", 0), ("random", 22)]
+    for order, param in cases:
+        ts = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lat = L.build(flags, g.periodic, order, param)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        t_asm = float(np.median(ts))
+        lay = quick_layout(flags, g.periodic, order, param, "f64")
+        lat = L.build(flags, g.periodic, order, param, stride=lay.stride)
+        prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), "f64", nontemporal=lay.nontemporal,
+                       xcd_chunk=lay.xcd_chunk)
+        st = L.init(lat, prm)
+        L.step(st, 2)
+        t, _ = timed(lambda: L.step(st, sweeps))
+        n = lat.n_fluid
+        emit({"experiment": "orderings", "workload": desc, "n_fluid": n, "order": order,
+              "param": param, "mflups": round(n * sweeps / t / 1e6, 1),
+              "gbs": round(376 * n * sweeps / t / 1e9, 1),
+              "hbm_frac": round(376 * n * sweeps / t / 1e9 / PEAK, 4),
+              "stride": lay.stride, "nt": lay.nontemporal, "chunk": lay.xcd_chunk,
+              "assembly_ms": round(t_asm * 1e3, 2),
+              "assembly_mcells_per_s": round(flags.numel() / t_asm / 1e6, 1)})
+        del lat, st
+        torch.cuda.empty_cache()

@@ -95,6 +95,20 @@ lbm_status launch_persistent_t(const TrtConst& c, int64_t n, int64_t stride, con
     if (!coop) return LBM_EHIP;
     LBM_TRY_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern),
                                                              kPBlock, 0));
+    // Co-residency is what the grid barrier needs.  Measured on gfx950: for
+    // the FP32 instance (72 VGPRs) the query reports 7 workgroups per CU but
+    // only 6 are resident at once (the arrival counter stalls after the first
+    // barrier at 7, completes at 6).  So the count is also bounded by the
+    // VGPR file at a 16-register granule, and by 4 workgroups per CU, which
+    // keeps 4 waves per SIMD for this bandwidth-bound loop.
+    hipFuncAttributes attr;
+    LBM_TRY_HIP(hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(kern)));
+    const int waves_per_simd = kPBlock / 64 / 4;  // one wave per SIMD per workgroup
+    if (attr.numRegs > 0) {
+        const int vgpr = (attr.numRegs + 15) / 16 * 16;
+        per_cu = std::min(per_cu, 512 / vgpr / waves_per_simd);
+    }
+    per_cu = std::min(per_cu, 4);
     int64_t grid = int64_t(per_cu) * cus;
     const int64_t tiles = (n + kPBlock - 1) / kPBlock;
     grid = std::min<int64_t>(grid, (tiles + NXCD - 1) / NXCD * NXCD);

@@ -248,3 +248,18 @@ def test_full_size_tube_sampled_step():
         assert rel_err_f64(f_next[:, a:b], orc[:, a:b]) <= TOL_F64
     # and the whole state conserves mass
     assert abs(f_next[:, :n].sum() - f_t[:, :n].sum()) <= 1e-12 * f_t[:, :n].sum()
+
+
+def test_large_packing_cropped_vs_oracle():
+    """The 512x512x1024 Boolean packing at 1/4 edge (128x128x256, porosity
+    0.4): bit-exact assembly and 10 FP64 sweeps within 1e-12 of the oracle."""
+    g = I.workload("large_packing", scale=4)
+    sp, lat = pair(g)
+    np.testing.assert_array_equal(lat.adj.cpu().numpy().view(np.uint32)[:, :sp.n_fluid],
+                                  sp.adj[:, :sp.n_fluid])
+    prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), "f64")
+    n = sp.n_fluid
+    f0 = random_state(n, 11, stride=lat.stride)
+    st = run_gpu(lat, prm, f0, 10)
+    orc = orun(prm, sp, f0, 10)
+    assert rel_err_f64(cells(st.f.cpu().numpy(), n), cells(orc, n)) <= TOL_F64
