@@ -64,7 +64,8 @@ def parse():
     ap.add_argument("--chunk", type=int, default=0,
                     help="consecutive tiles per XCD for --layout given (0 = one eighth each)")
     ap.add_argument("--experiment", default="headline",
-                    choices=["headline", "precision", "adjoint", "batched", "orderings"],
+                    choices=["headline", "precision", "adjoint", "batched", "orderings",
+                             "partitions", "ordering_tuner"],
                     help="headline: the JSON line below; the others print one JSON line per "
                          "configuration (see the module docstring)")
     ap.add_argument("--scale", type=int, default=1,

@@ -17,7 +17,7 @@ from paper_1111_1129_amd import _native as N
 from paper_1111_1129_amd import adjoint as AD
 from paper_1111_1129_amd import inputs as I
 from paper_1111_1129_amd import lattice as L
-from paper_1111_1129_amd.tune import tune_layout, candidate_strides
+from paper_1111_1129_amd.tune import tune_layout, tune_ordering, candidate_strides
 
 BYTES = {"f64": 376, "f64s": 376, "f32": 224, "f32s": 224, "f16s": 148}
 PEAK = 8000.0
@@ -223,7 +223,7 @@ def orderings(a):
     flags = dev_flags(g)
     sweeps = 200
     cases = [("lex", 0)] + [("blocked", b) for b in (2, 4, 8, 16, 32, 64, 100)] + \
-        [("morton1", 0), ("morton2", 0), ("random", 22)]
+        [("morton1", 0), ("morton2", 0), ("hilbert", 0), ("random", 22)]
     for order, param in cases:
         ts = []
         for _ in range(3):
@@ -250,3 +250,44 @@ def orderings(a):
               "assembly_mcells_per_s": round(flags.numel() / t_asm / 1e6, 1)})
         del lat, st
         torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------------------
+def partitions(a):
+    """The paper's Fig. 7 analysis on one GPU: neighbour chunks and remote
+    links per chunk when the list is cut into G chunks, per ordering, for
+    the paper's 500x100x100 channel and for the tube packing."""
+    for name, g in (("channel", I.channel(100)), ("tube_packing", I.packing_tube(2))):
+        flags = dev_flags(g)
+        for order, param in [("lex", 0), ("blocked", 8), ("blocked", 32), ("blocked", 100),
+                             ("morton1", 0), ("morton2", 0), ("hilbert", 0)]:
+            lat = L.build(flags, g.periodic, order, param)
+            for G in (8, 64, 512, 3072):
+                t, (r, nb, ifc) = timed(lambda: L.partition_stats(lat, G))
+                r, nb = r.double(), nb.double()
+                emit({"experiment": "partitions", "workload": name, "n_fluid": lat.n_fluid,
+                      "order": order, "param": param, "chunks": G,
+                      "cells_per_chunk": lat.n_fluid / G,
+                      "neighbours_mean": round(float(nb.mean()), 2),
+                      "neighbours_max": int(nb.max()),
+                      "remote_links_mean": round(float(r.mean()), 1),
+                      "remote_links_max": int(r.max()),
+                      "remote_links_total": int(r.sum()),
+                      "interface_cells_mean": round(float(ifc.double().mean()), 1),
+                      "analysis_ms": round(t * 1e3, 3)})
+            del lat
+
+
+def ordering_tuner(a):
+    """Automatic choice of ordering: candidates timed on a 1/8 sample of the
+    geometry (the paper's proposal, Sec. 8) and on the whole geometry."""
+    g = I.packing_tube(2)
+    flags = dev_flags(g)
+    for sample in (0.125, None):
+        t0 = time.perf_counter()
+        order, param, lay, table = tune_ordering(flags, g.periodic, "f64", sample=sample)
+        dt = time.perf_counter() - t0
+        emit({"experiment": "ordering_tuner", "sample": sample, "chosen": [order, param],
+              "layout": [lay.stride, lay.nontemporal, lay.xcd_chunk],
+              "full_geometry_mflups": round(lay.mflups, 1), "tuning_s": round(dt, 2),
+              "candidates": table})

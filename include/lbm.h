@@ -64,11 +64,15 @@ typedef enum {
     LBM_ORDER_MORTON1 = 2, /* Z curve, 1-bit interleave: bit k of x,y,z -> bit 3k,3k+1,3k+2 */
     LBM_ORDER_MORTON2 = 3, /* Z curve, 2-bit groups: bits [2k,2k+2) of x,y,z -> [6k,6k+2),
                               [6k+2,6k+4), [6k+4,6k+6) */
-    LBM_ORDER_RANDOM = 4   /* key = 4-round Feistel bijection of lin on [0, 4^h),
+    LBM_ORDER_RANDOM = 4,  /* key = 4-round Feistel bijection of lin on [0, 4^h),
                               4^h >= box (smallest h >= 1); round r maps (L,R) ->
                               (R, L ^ (splitmix64(seed ^ (r << 32) ^ R) & (2^h - 1)));
                               seed = order_param.  A control ordering: the paper
                               allows any injective index function. */
+    LBM_ORDER_HILBERT = 5  /* Hilbert curve on the enclosing 2^B cube (Sec. 3 names it):
+                              Skilling's transposed index (AIP Conf. Proc. 707, 2004)
+                              of (x, y, z), read level by level with x's bit the most
+                              significant of each 3-bit digit */
 } lbm_order;
 
 /* PDF storage (the paper stores double precision, Sec. 7).  "Shifted" arrays
@@ -252,6 +256,29 @@ lbm_status lbm_moments(const lbm_params* p, int64_t n, int64_t stride, const uin
                        const void* f, double* rho, double* u, const lbm_segment* seg,
                        int32_t n_seg, double* totals, void* workspace, size_t* ws_bytes,
                        void* stream);
+
+/*
+ * lbm_partition_stats -- communication metrics of cutting the list into
+ * n_chunks near-equal chunks (Sec. 2: a solver on N processes cuts the 1-D
+ * list into N equal chunks, some smaller by one cell; Sec. 7 and Fig. 7:
+ * number of neighbour partitions and of remote links per partition).
+ *
+ * Chunk k holds list cells [floor(k n / G), floor((k+1) n / G)), G = n_chunks.
+ * A remote link is an adjacency entry of a cell in chunk a that streams
+ * (not bounce-back) from a cell of another chunk b: the PDF chunk a would
+ * have to receive each step.  Per chunk it reports:
+ *  remote_links    int64 [G]: number of remote links;
+ *  neighbours      int32 [G]: number of distinct chunks it pulls from (the
+ *                  relation is symmetric for a pull adjacency);
+ *  interface_cells int32 [G]: cells with at least one remote link.
+ *  workspace, ws_bytes: scratch (query with workspace == NULL).
+ * Errors: LBM_EINVAL (n_chunks <= 0 or > 16384, n <= 0, NULL outputs),
+ * LBM_EOVERFLOW, LBM_EWORKSPACE, LBM_EHIP.
+ */
+lbm_status lbm_partition_stats(int64_t n, int64_t stride, const uint32_t* adj, int64_t n_chunks,
+                               int64_t* remote_links, int32_t* neighbours,
+                               int32_t* interface_cells, void* workspace, size_t* ws_bytes,
+                               void* stream);
 
 /* Library version (major*10000 + minor*100 + patch) and a static string for a
  * status code.  Both are host-only and allocate nothing. */

@@ -35,7 +35,7 @@ _LIB_PATH = os.path.join(_HERE, "_liblbm_oracle.so")
 _lock = threading.Lock()
 _lib = None
 
-ORDERS = {"lex": 0, "blocked": 1, "morton1": 2, "morton2": 3, "random": 4}
+ORDERS = {"lex": 0, "blocked": 1, "morton1": 2, "morton2": 3, "random": 4, "hilbert": 5}
 OK, EINVAL, ECAPACITY, EOVERFLOW = 0, -1, -2, -3
 
 
@@ -326,3 +326,41 @@ def complex_step_derivative(prm: TRT, adj, f0, ns, direction, n_steps: int, shif
         step(prm, adj, a, b, ns=nsc)
         a, b = b, a
     return float(objective(prm, adj, a, shifted).imag / h)
+
+
+# ---------------------------------------------------------------------------
+# communication analysis of a list cut into chunks (paper Sec. 2, Sec. 7)
+# ---------------------------------------------------------------------------
+
+def chunk_bounds(n: int, G: int) -> np.ndarray:
+    """Start of each of G chunks of an n-cell list, plus n: chunk k is
+    [floor(k n / G), floor((k+1) n / G))."""
+    return np.array([(k * n) // G for k in range(G + 1)], dtype=np.int64)
+
+
+def partition_stats(adj: np.ndarray, n: int, G: int):
+    """(remote_links[G], neighbours[G], interface_cells[G]) by definition:
+    entry k of cell m streams from cell src when the slot's direction is k+1;
+    it is a remote link when src's chunk differs from m's."""
+    stride = adj.shape[1]
+    bounds = chunk_bounds(n, G)
+    cells = np.arange(n)
+    own = np.searchsorted(bounds, cells, side="right") - 1
+    remote = np.zeros(G, dtype=np.int64)
+    pairs = set()
+    has_remote = np.zeros(n, dtype=bool)
+    for k in range(18):
+        slot = adj[k, :n].astype(np.int64)
+        streams = slot // stride == k + 1
+        src = slot - (k + 1) * stride
+        src_chunk = np.where(streams, np.searchsorted(bounds, np.where(streams, src, 0),
+                                                      side="right") - 1, own)
+        cross = streams & (src_chunk != own)
+        remote += np.bincount(own[cross], minlength=G)
+        has_remote |= cross
+        pairs.update(zip(own[cross].tolist(), src_chunk[cross].tolist()))
+    neighbours = np.zeros(G, dtype=np.int64)
+    for a, _ in pairs:
+        neighbours[a] += 1
+    interface = np.bincount(own[has_remote], minlength=G)
+    return remote, neighbours, interface

@@ -15,8 +15,9 @@
  *  - Numbering scheme (Sec. 3, "Numbering scheme"): every box cell, fluid or
  *    solid, gets a unique key I(x,y,z) from an injective index function:
  *    lexicographic with or without blocking, Z curve with 1-bit or 2-bit
- *    interleave (Sec. 7, single node performance), or any injective f -- here
- *    a keyed Feistel bijection for a random control ordering.
+ *    interleave (Sec. 7, single node performance), the Hilbert curve (named
+ *    in Sec. 3), or any injective f -- here a keyed Feistel bijection for a
+ *    random control ordering.
  *  - Contiguous index (Sec. 3, "Contiguous index generation"): fluid cells
  *    get I_c = their rank among fluid keys.  The paper's octree merge of
  *    incell runs computes exactly this rank; the oracle computes it by
@@ -51,7 +52,8 @@
 #define ORC_ECAPACITY (-2)
 #define ORC_EOVERFLOW (-3)
 
-enum { ORD_LEX = 0, ORD_BLOCKED = 1, ORD_MORTON1 = 2, ORD_MORTON2 = 3, ORD_RANDOM = 4 };
+enum { ORD_LEX = 0, ORD_BLOCKED = 1, ORD_MORTON1 = 2, ORD_MORTON2 = 3, ORD_RANDOM = 4,
+       ORD_HILBERT = 5 };
 
 /* ---- D3Q19 velocity set: rest, 6 axis links, 12 diagonal links.
  * Opposite pairs are (1,2), (3,4), ..., (17,18). */
@@ -111,6 +113,47 @@ uint64_t orc_feistel(uint64_t seed, int h, uint64_t v) {
     return (L << h) | R;
 }
 
+/* Hilbert curve key on the 2^B cube (Skilling, "Programming the Hilbert
+ * curve", AIP Conf. Proc. 707, 2004).  The coordinates are turned into the
+ * "transposed" Hilbert index: from the top level down, every lower-order
+ * bit pattern is reflected or exchanged with the x word so that each
+ * sub-cube is entered in the orientation the curve needs, then the three
+ * words are Gray-coded.  The key reads the transposed words level by level,
+ * x's bit the most significant of each 3-bit digit. */
+static uint64_t hilbert_key(int B, uint64_t x, uint64_t y, uint64_t z) {
+    if (B == 0) return 0;
+    uint64_t X[3] = {x, y, z};
+    const uint64_t top = (uint64_t)1 << (B - 1);
+    for (uint64_t q = top; q > 1; q >>= 1) {
+        const uint64_t low = q - 1;
+        for (int i = 0; i < 3; ++i) {
+            if (X[i] & q) {
+                X[0] ^= low;
+            } else {
+                uint64_t swap = (X[0] ^ X[i]) & low;
+                X[0] ^= swap;
+                X[i] ^= swap;
+            }
+        }
+    }
+    X[1] ^= X[0];
+    X[2] ^= X[1];
+    uint64_t flip = 0;
+    for (uint64_t q = top; q > 1; q >>= 1)
+        if (X[2] & q) flip ^= q - 1;
+    for (int i = 0; i < 3; ++i) X[i] ^= flip;
+    uint64_t key = 0;
+    for (int j = B - 1; j >= 0; --j)
+        for (int i = 0; i < 3; ++i) key = (key << 1) | ((X[i] >> j) & 1);
+    return key;
+}
+
+static int bits_to_hold(int64_t n) {
+    int b = 0;
+    while (((int64_t)1 << b) < n) ++b;
+    return b;
+}
+
 /* Key I(x,y,z) of a box cell for the given ordering. */
 uint64_t orc_key(int order, uint64_t param, int64_t nx, int64_t ny, int64_t nz,
                  int64_t x, int64_t y, int64_t z) {
@@ -153,6 +196,11 @@ uint64_t orc_key(int order, uint64_t param, int64_t nx, int64_t ny, int64_t nz,
         uint64_t n_box = (uint64_t)(nx * ny * nz);
         return orc_feistel(param, orc_feistel_half_bits(n_box), lin);
     }
+    case ORD_HILBERT: {
+        int64_t dmax = nx > ny ? nx : ny;
+        if (nz > dmax) dmax = nz;
+        return hilbert_key(bits_to_hold(dmax), (uint64_t)x, (uint64_t)y, (uint64_t)z);
+    }
     default:
         return 0;
     }
@@ -187,7 +235,7 @@ int orc_build(int64_t nx, int64_t ny, int64_t nz, uint32_t periodic, int order,
               int32_t* index_of, int32_t* cell_of, uint32_t* adj, int64_t cap,
               int64_t* n_fluid) {
     if (nx <= 0 || ny <= 0 || nz <= 0 || !flag || !n_fluid) return ORC_EINVAL;
-    if (order < ORD_LEX || order > ORD_RANDOM) return ORC_EINVAL;
+    if (order < ORD_LEX || order > ORD_HILBERT) return ORC_EINVAL;
     if (order == ORD_BLOCKED && param == 0) return ORC_EINVAL;
     int64_t n_box = nx * ny * nz;
     if (n_box >= ((int64_t)1 << 31)) return ORC_EOVERFLOW;

@@ -17,14 +17,17 @@ from .inputs import Geometry  # noqa: F401  (seeded synthetic inputs)
 def __getattr__(name):
     # lazy: keep `import paper_1111_1129_amd.inputs` free of torch and HIP
     if name in ("build", "init", "step", "moments", "params", "set_state", "count_fluid",
-                "Lattice", "State", "Batch"):
+                "partition_stats", "aligned_stride", "Lattice", "State", "Batch"):
         from . import lattice
         return getattr(lattice, name)
     if name in ("PermeabilityFn", "adjoint_gradient", "forward_states"):
         from . import adjoint
         return getattr(adjoint, name)
+    if name in ("tune_layout", "tune_ordering"):
+        from . import tune
+        return getattr(tune, name)
     if name in ("lbm_build_adjacency", "lbm_init", "lbm_step", "lbm_step_adjoint", "lbm_moments",
-                "lbm_version", "LbmError"):
+                "lbm_partition_stats", "lbm_version", "LbmError"):
         from . import _native
         return getattr(_native, name)
     raise AttributeError(name)

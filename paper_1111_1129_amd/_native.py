@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_PKG, "liblbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ECAPACITY, LBM_EOVERFLOW, LBM_EWORKSPACE, LBM_EHIP, LBM_EBARRIER = \
     0, -1, -2, -3, -4, -5, -6
-ORDERS = {"lex": 0, "blocked": 1, "morton1": 2, "morton2": 3, "random": 4}
+ORDERS = {"lex": 0, "blocked": 1, "morton1": 2, "morton2": 3, "random": 4, "hilbert": 5}
 STORAGES = {"f64": 0, "f64s": 1, "f32": 2, "f32s": 3, "f16s": 4}
 STORAGE_DTYPE = {0: torch.float64, 1: torch.float64, 2: torch.float32, 3: torch.float32,
                  4: torch.float16}
@@ -26,7 +26,7 @@ FLAG_NONTEMPORAL = 1
 FLAG_XCD_CHUNK_SHIFT = 8
 
 ENTRY_POINTS = ("lbm_build_adjacency", "lbm_init", "lbm_step", "lbm_step_adjoint",
-                "lbm_moments", "lbm_version", "lbm_status_string")
+                "lbm_moments", "lbm_partition_stats", "lbm_version", "lbm_status_string")
 
 
 class lbm_geom(C.Structure):
@@ -79,6 +79,8 @@ def load(path: str = LIB_PATH):
         lib.lbm_moments.restype = I32
         lib.lbm_moments.argtypes = [C.POINTER(lbm_params), I64, I64, P, P, P, P, P, I32, P, P,
                                     C.POINTER(SZ), P]
+        lib.lbm_partition_stats.restype = I32
+        lib.lbm_partition_stats.argtypes = [I64, I64, P, I64, P, P, P, P, C.POINTER(SZ), P]
         lib.lbm_version.restype = I32
         lib.lbm_version.argtypes = []
         lib.lbm_status_string.restype = C.c_char_p
@@ -175,6 +177,17 @@ def lbm_moments(params: lbm_params, n, stride, adj, f, rho, u, segments, totals,
     st = lib.lbm_moments(C.byref(params), n, stride, _ptr(adj), _ptr(f), _ptr(rho), _ptr(u), seg,
                          n_seg, _ptr(totals), None if query else _ptr(workspace), C.byref(ws),
                          _stream(stream))
+    return st, ws.value
+
+
+def lbm_partition_stats(n, stride, adj, n_chunks, remote_links, neighbours, interface_cells,
+                        workspace=None, ws_bytes=0, stream=None, query=False):
+    lib = load()
+    ws = C.c_size_t(ws_bytes)
+    st = lib.lbm_partition_stats(n, stride, _ptr(adj), n_chunks, _ptr(remote_links),
+                                 _ptr(neighbours), _ptr(interface_cells),
+                                 None if query else _ptr(workspace), C.byref(ws),
+                                 None if query else _stream(stream))
     return st, ws.value
 
 

@@ -18,7 +18,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB_PATH = os.path.join(PKG, "liblbm.so")
-SOURCES = ["assembly.hip", "trt.hip", "persistent.hip", "moments.hip", "adjoint.hip", "abi.cpp"]
+SOURCES = ["assembly.hip", "trt.hip", "persistent.hip", "moments.hip", "adjoint.hip",
+           "partition.hip", "abi.cpp"]
 ARCH = "gfx950"
 
 

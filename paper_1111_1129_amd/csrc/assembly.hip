@@ -20,9 +20,9 @@
 //
 // Key positions: lexicographic and blocked orders are walked through a
 // gap-free "compact" position that decodes directly to the cell holding that
-// rank among box cells; the Z curves and the random order walk their own key
-// space (a power of two, at most 8x the box) and skip positions that decode
-// outside the box.
+// rank among box cells; the Z curves, the Hilbert curve and the random order
+// walk their own key space (a power of two, at most 8x the box) and skip
+// positions that decode outside the box.
 #include <algorithm>
 
 #include "lbm_device.hpp"
@@ -67,6 +67,41 @@ __device__ inline uint64_t feistel_inverse(uint64_t seed, int h, uint64_t v) {
     return (L << h) | R;
 }
 
+// Cell of the Hilbert key p on the 2^B cube: split p into the three
+// transposed words (x's bit the most significant of each 3-bit digit), undo
+// the Gray code, then undo the per-level reflections and exchanges from the
+// lowest level up (the inverse of Skilling's coordinates-to-index transform).
+__device__ inline void hilbert_decode(uint64_t p, int B, int64_t& x, int64_t& y, int64_t& z) {
+    uint32_t X[3] = {0u, 0u, 0u};
+    for (int j = 0; j < B; ++j) {
+        X[0] |= uint32_t((p >> (3 * j + 2)) & 1) << j;
+        X[1] |= uint32_t((p >> (3 * j + 1)) & 1) << j;
+        X[2] |= uint32_t((p >> (3 * j)) & 1) << j;
+    }
+    if (B > 0) {
+        const uint32_t end = 2u << (B - 1);
+        uint32_t t = X[2] >> 1;
+        X[2] ^= X[1];
+        X[1] ^= X[0];
+        X[0] ^= t;
+        for (uint32_t q = 2; q != end; q <<= 1) {
+            const uint32_t low = q - 1;
+            for (int i = 2; i >= 0; --i) {
+                if (X[i] & q) {
+                    X[0] ^= low;
+                } else {
+                    const uint32_t swap = (X[0] ^ X[i]) & low;
+                    X[0] ^= swap;
+                    X[i] ^= swap;
+                }
+            }
+        }
+    }
+    x = X[0];
+    y = X[1];
+    z = X[2];
+}
+
 // Box cell (linear index) at key position p, or -1 if p is a gap.
 __device__ inline int64_t decode(const KeySpace& ks, uint64_t p) {
     const int64_t nx = ks.nx, ny = ks.ny, nz = ks.nz;
@@ -109,6 +144,12 @@ __device__ inline int64_t decode(const KeySpace& ks, uint64_t p) {
             y |= int64_t((p >> (6 * k + 2)) & 3) << (2 * k);
             z |= int64_t((p >> (6 * k + 4)) & 3) << (2 * k);
         }
+        if (x >= nx || y >= ny || z >= nz) return -1;
+        return x + nx * (y + ny * z);
+    }
+    case LBM_ORDER_HILBERT: {
+        int64_t x, y, z;
+        hilbert_decode(p, ks.groups, x, y, z);
         if (x >= nx || y >= ny || z >= nz) return -1;
         return x + nx * (y + ny * z);
     }
@@ -280,7 +321,8 @@ static lbm_status make_keyspace(const lbm_geom& g, KeySpace& ks) {
         ks.b = std::min<int64_t>(int64_t(g.order_param), dmax);
         ks.positions = uint64_t(n_box);
         break;
-    case LBM_ORDER_MORTON1: {
+    case LBM_ORDER_MORTON1:
+    case LBM_ORDER_HILBERT: {
         ks.groups = bits_for(dmax);
         if (3 * ks.groups > 62) return LBM_EOVERFLOW;
         ks.positions = uint64_t(1) << (3 * ks.groups);

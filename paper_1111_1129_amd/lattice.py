@@ -181,6 +181,24 @@ def moments(state: State, fields: bool = True, segments=None, stream=None):
     return rho, u, totals
 
 
+def partition_stats(lat: Lattice, n_chunks: int, n: int | None = None, stream=None):
+    """(remote_links int64[G], neighbours int32[G], interface_cells int32[G])
+    of cutting the list [0, n) into n_chunks near-equal chunks (paper Sec. 2,
+    Sec. 7 / Fig. 7)."""
+    n = lat.base + lat.n_fluid if n is None else n
+    dev = lat.device
+    remote = torch.empty(n_chunks, dtype=torch.int64, device=dev)
+    nb = torch.empty(n_chunks, dtype=torch.int32, device=dev)
+    iface = torch.empty(n_chunks, dtype=torch.int32, device=dev)
+    st, wsn = N.lbm_partition_stats(n, lat.stride, lat.adj, n_chunks, remote, nb, iface, query=True)
+    N._check("lbm_partition_stats", st)
+    ws = torch.empty(wsn, dtype=torch.uint8, device=dev)
+    st, _ = N.lbm_partition_stats(n, lat.stride, lat.adj, n_chunks, remote, nb, iface, ws, wsn,
+                                  stream)
+    N._check("lbm_partition_stats", st)
+    return remote, nb, iface
+
+
 class Batch:
     """Many geometries in one set of [19][S] / [18][S] arrays.
 

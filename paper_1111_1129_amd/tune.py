@@ -74,3 +74,46 @@ def tune_layout(flags: torch.Tensor, periodic: int, order: str = "lex", param: i
         del lat
     best.table = table
     return best
+
+
+ORDER_CANDIDATES = (("lex", 0), ("blocked", 8), ("blocked", 16), ("blocked", 32),
+                    ("blocked", 64), ("morton2", 0), ("hilbert", 0))
+
+
+def crop_sample(flags: torch.Tensor, fraction: float) -> torch.Tensor:
+    """Central sub-box holding about `fraction` of the cells (same aspect)."""
+    nz, ny, nx = flags.shape
+    f = fraction ** (1.0 / 3.0)
+    sz, sy, sx = (max(1, int(round(d * f))) for d in (nz, ny, nx))
+    z0, y0, x0 = (nz - sz) // 2, (ny - sy) // 2, (nx - sx) // 2
+    return flags[z0:z0 + sz, y0:y0 + sy, x0:x0 + sx].contiguous()
+
+
+def tune_ordering(flags: torch.Tensor, periodic: int, storage: str = "f64",
+                  candidates=ORDER_CANDIDATES, sample: float | None = None,
+                  force=(1e-6, 0.0, 0.0), sweeps: int = 4):
+    """Pick the cell ordering (and layout) with the highest sweep rate.
+
+    The paper proposes choosing the blocking factor by simulating samples of
+    the geometry (Sec. 8); with `sample` the candidates are timed on the
+    central sub-box holding that fraction of the cells, otherwise on the
+    whole geometry.  Returns (order, param, Layout, table).
+    """
+    probe = crop_sample(flags, sample) if sample else flags
+    # in a crop the y/z walls may be cut away; periodicity is kept as given
+    best = None
+    table = []
+    for order, param in candidates:
+        n = L.count_fluid(probe, periodic, order, param)
+        if n == 0:
+            continue
+        lay = tune_layout(probe, periodic, order, param, storage, force, sweeps=sweeps,
+                          candidates=sorted({L.aligned_stride(n), candidate_strides(n)[-3]}),
+                          chunks=(1, 0))
+        table.append((order, param, round(lay.mflups, 1)))
+        if best is None or lay.mflups > best[2].mflups:
+            best = (order, param, lay)
+    order, param, lay = best
+    if sample:  # re-tune the layout of the chosen ordering on the full geometry
+        lay = tune_layout(flags, periodic, order, param, storage, force, sweeps=sweeps)
+    return order, param, lay, table

@@ -15,7 +15,7 @@ from gpu_helpers import adj_u32, dev_flags, print_case
 pytestmark = pytest.mark.gpu
 
 ORDERS = [("lex", 0), ("blocked", 16), ("blocked", 3), ("blocked", 1), ("morton1", 0),
-          ("morton2", 0), ("random", 22)]
+          ("morton2", 0), ("random", 22), ("hilbert", 0)]
 
 
 def assert_same(geom, order, param, base=0, stride=None):
@@ -40,7 +40,7 @@ def test_exhaustive_2x2x2(dev):
         flags = np.array([(bits >> k) & 1 for k in range(8)], dtype=np.uint8).reshape(2, 2, 2)
         for periodic in (0, 5, 7):
             for order, param in [("lex", 0), ("blocked", 2), ("morton1", 0), ("morton2", 0),
-                                 ("random", 3)]:
+                                 ("random", 3), ("hilbert", 0)]:
                 g = I.Geometry("tiny", flags, periodic)
                 lat = L.build(dev_flags(g), periodic, order, param)
                 sp = O.build(flags, periodic, order, param, stride=lat.stride)
@@ -103,7 +103,7 @@ def tube():
 
 
 @pytest.mark.parametrize("order,param", [("lex", 0), ("blocked", 16), ("morton1", 0),
-                                         ("morton2", 0), ("random", 22)])
+                                         ("morton2", 0), ("random", 22), ("hilbert", 0)])
 def test_tube_full_size(tube, order, param):
     lat, sp = assert_same(tube, order, param)
     # adjacency is a permutation of the PDF slots (pull streaming is bijective)
@@ -115,3 +115,28 @@ def test_tube_full_size(tube, order, param):
     counts = np.bincount(dense.ravel(), minlength=19 * n)
     assert counts.shape == (19 * n,)
     assert (counts[:n] == 0).all() and (counts[n:] == 1).all()
+
+
+@pytest.mark.parametrize("order,param", [("lex", 0), ("blocked", 8), ("hilbert", 0)])
+@pytest.mark.parametrize("G", [1, 2, 7, 64, 300])
+def test_partition_stats_vs_oracle(order, param, G):
+    g = I.packing_small(1)
+    lat = L.build(dev_flags(g), g.periodic, order, param)
+    sp = O.build(g.flags, g.periodic, order, param, stride=lat.stride)
+    r, nb, ifc = L.partition_stats(lat, G)
+    orr, onb, oifc = O.partition_stats(sp.adj, sp.n_fluid, G)
+    np.testing.assert_array_equal(r.cpu().numpy(), orr)
+    np.testing.assert_array_equal(nb.cpu().numpy(), onb)
+    np.testing.assert_array_equal(ifc.cpu().numpy(), oifc)
+
+
+def test_partition_stats_tube_3072_chunks(tube):
+    """The tube cut into 3072 chunks (the paper's largest process count):
+    bit-exact against the oracle's definition."""
+    lat = L.build(dev_flags(tube), tube.periodic, "blocked", 16)
+    sp = O.build(tube.flags, tube.periodic, "blocked", 16, stride=lat.stride)
+    r, nb, ifc = L.partition_stats(lat, 3072)
+    orr, onb, oifc = O.partition_stats(sp.adj, sp.n_fluid, 3072)
+    np.testing.assert_array_equal(r.cpu().numpy(), orr)
+    np.testing.assert_array_equal(nb.cpu().numpy(), onb)
+    np.testing.assert_array_equal(ifc.cpu().numpy(), oifc)

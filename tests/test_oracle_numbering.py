@@ -313,3 +313,92 @@ def test_channel_fluid_count_matches_paper():
     sp = O.build(g.flags, g.periodic, "lex")
     assert sp.n_fluid == 500 * 98 * 98
     assert abs(sp.n_fluid - stated["channel_500x100x100_fluid"]) <= 0.05e6
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_hilbert_is_a_continuous_curve(k):
+    """On a full 2^k cube the Hilbert order visits every cell once, starts at
+    the origin, and consecutive cells are face neighbours (the defining
+    property of a Hilbert curve; the Z curves fail it)."""
+    n = 2 ** k
+    g = I.all_fluid(n, n, n)
+    sp = O.build(g.flags, 7, "hilbert")
+    lin = sp.cell_of.astype(np.int64)
+    xyz = np.stack([lin % n, (lin // n) % n, lin // (n * n)], axis=1)
+    assert sorted(lin.tolist()) == list(range(n ** 3))
+    assert tuple(xyz[0]) == (0, 0, 0)
+    steps = np.abs(np.diff(xyz, axis=0)).sum(axis=1)
+    assert (steps == 1).all()
+    if k >= 2:
+        z = O.build(g.flags, 7, "morton1").cell_of.astype(np.int64)
+        zxyz = np.stack([z % n, (z // n) % n, z // (n * n)], axis=1)
+        assert (np.abs(np.diff(zxyz, axis=0)).sum(axis=1) > 1).any()
+
+
+def test_hilbert_on_uneven_boxes_is_a_bijection():
+    for dims in [(3, 5, 7), (9, 2, 4), (1, 1, 6), (17, 3, 1)]:
+        g = I.random_flags(sum(dims), *dims, fluid_fraction=0.7)
+        sp = O.build(g.flags, g.periodic, "hilbert")
+        check_adjacency_bruteforce(g.flags, g.periodic, sp)
+        keys = [O.key("hilbert", 0, dims, l % dims[0], (l // dims[0]) % dims[1],
+                      l // (dims[0] * dims[1])) for l in sp.cell_of]
+        assert all(a < b for a, b in zip(keys, keys[1:]))
+        allk = {O.key("hilbert", 0, dims, x, y, z) for x in range(dims[0])
+                for y in range(dims[1]) for z in range(dims[2])}
+        assert len(allk) == dims[0] * dims[1] * dims[2]
+
+
+# ---- chunk communication analysis ----------------------------------------
+
+def test_partition_chunks_are_near_equal():
+    """The list is cut into G chunks whose sizes differ by at most one cell
+    (paper Sec. 2)."""
+    for n, G in [(10, 3), (17263, 7), (100, 100), (5, 5), (1000, 64)]:
+        b = O.chunk_bounds(n, G)
+        sizes = np.diff(b)
+        assert b[0] == 0 and b[-1] == n and sizes.max() - sizes.min() <= 1
+
+
+def test_partition_stats_special_cases_and_symmetry():
+    g = I.packing_small(1)
+    sp = O.build(g.flags, g.periodic, "lex")
+    n = sp.n_fluid
+    # one chunk: nothing is remote
+    r, nb, ifc = O.partition_stats(sp.adj, n, 1)
+    assert r.sum() == 0 and nb.sum() == 0 and ifc.sum() == 0
+    # every cell its own chunk: every streaming entry is remote
+    r, nb, ifc = O.partition_stats(sp.adj, n, n)
+    S = sp.adj.shape[1]
+    streaming = sum(int((sp.adj[k, :n].astype(np.int64) // S == k + 1).sum()) for k in range(18))
+    assert r.sum() == streaming
+    # pull symmetry: links a<-b and b<-a come in pairs, so the total is even
+    # and chunk neighbour relations are symmetric
+    for G in (2, 5, 16, 64):
+        r, nb, ifc = O.partition_stats(sp.adj, n, G)
+        assert r.sum() % 2 == 0 and (ifc <= np.diff(O.chunk_bounds(n, G))).all()
+        assert (nb <= G - 1).all() and (r >= ifc).all()
+
+
+def test_partition_stats_brute_force_small():
+    """A 4x3x2 all-fluid periodic box cut in two: count links by walking the
+    D3Q19 neighbourhood of every cell by hand."""
+    g = I.all_fluid(4, 3, 2)
+    sp = O.build(g.flags, 7, "lex")
+    n = sp.n_fluid
+    c, opp = d3q19()
+    G = 2
+    b = O.chunk_bounds(n, G)
+    chunk = lambda m: int(np.searchsorted(b, m, side="right") - 1)
+    expect = np.zeros(G, dtype=np.int64)
+    for x in range(4):
+        for y in range(3):
+            for z in range(2):
+                m = x + 4 * (y + 3 * z)
+                for i in range(1, 19):
+                    u = ((x - c[i][0]) % 4, (y - c[i][1]) % 3, (z - c[i][2]) % 2)
+                    src = u[0] + 4 * (u[1] + 3 * u[2])
+                    if chunk(src) != chunk(m):
+                        expect[chunk(m)] += 1
+    r, nb, _ = O.partition_stats(sp.adj, n, G)
+    np.testing.assert_array_equal(r, expect)
+    assert list(nb) == [1, 1]
