@@ -57,7 +57,7 @@ def precision(a):
     flags = dev_flags(g)
     sweeps = 500
     forms = ["f64", "f64s", "f32", "f32s", "f16s"]
-    layouts = {st: quick_layout(flags, g.periodic, "lex", 0, st) for st in forms}
+    layouts = {st: tune_layout(flags, g.periodic, "lex", 0, st, sweeps=4) for st in forms}
     for gx in (1e-6, 1e-5, 1e-4):
         ref = None
         t_ref = None
@@ -90,6 +90,39 @@ def precision(a):
             emit(rec)
             del lat, state, u
             torch.cuda.empty_cache()
+    precision_vs_oracle(a)
+
+
+def precision_vs_oracle(a, scale=4, sweeps=500):
+    """Every storage form against the FP64 oracle itself, on the 1/4-edge
+    crop of the precision workload (128 x 128 x 256, porosity 0.4), plus the
+    oracle's own rate on the host cores."""
+    import oracle as O
+    g = I.workload("large_packing", scale=scale)
+    sp = O.build(g.flags, g.periodic, "lex")
+    n = sp.n_fluid
+    oprm = O.TRT(0.8, 3 / 16, (1e-6, 0.0, 0.0))
+    f = O.init(n)
+    t0 = time.perf_counter()
+    f = O.run(oprm, sp.adj, f, sweeps)
+    t_cpu = time.perf_counter() - t0
+    _, u_orc, _ = O.moments(oprm, sp.adj, f)
+    u_orc = torch.from_numpy(np.ascontiguousarray(u_orc)).cuda()
+    flags = dev_flags(g)
+    lat = L.build(flags, g.periodic, "lex")
+    for st in ("f64", "f64s", "f32", "f32s", "f16s"):
+        prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), st)
+        state = L.init(lat, prm)
+        L.step(state, sweeps)
+        _, u, _ = L.moments(state)
+        d = u - u_orc
+        emit({"experiment": "precision_vs_oracle", "workload": f"large_packing/{scale}",
+              "n_fluid": n, "sweeps": sweeps, "storage": st, "gx": 1e-6,
+              "u_rel_l2_vs_oracle": float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(u_orc)),
+              "u_rel_max_vs_oracle": float(d.abs().max() / u_orc.abs().max()),
+              "cpu_baseline": {"value": round(n * sweeps / t_cpu / 1e6, 2), "unit": "MFLUPS",
+                               "cores": O.max_threads(), "kind": "oracle",
+                               "sample": f"{sweeps} FP64 sweeps of the {n}-cell crop"}})
 
 
 # ---------------------------------------------------------------------------
@@ -153,6 +186,26 @@ def adjoint(a):
     rich = (100 * np.array(fds[1e-3]) - np.array(fds[1e-2])) / 99
     per_h["richardson_1e-2_1e-3"] = np.abs(g32 - rich) / np.abs(rich)
     errs = per_h[1e-4]
+    import oracle as O
+    osp = O.build(g.flags, g.periodic, "lex")
+    oprm = O.TRT(0.8, 3 / 16, (1e-6, 0.0, 0.0))
+    ons = np.ascontiguousarray(g.ns.ravel()[osp.cell_of])
+    of = O.init(osp.n_fluid, shifted=True)
+    og = np.empty_like(of)
+    ol, ol2, ogr = np.zeros_like(of), np.zeros_like(of), np.zeros(osp.n_fluid)
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        O.step(oprm, osp.adj, of, og, ns=ons)
+    t_of = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        O.adjoint_step(oprm, osp.adj, of, ons, ol, ol2, ogr)
+    t_oa = (time.perf_counter() - t0) / reps
+    cpu = {"value": round(osp.n_fluid / (t_of + t_oa) / 1e6, 2), "unit": "M cell-steps/s",
+           "cores": O.max_threads(), "kind": "oracle",
+           "sample": f"{reps} forward + {reps} adjoint FP64 steps of the same box",
+           "forward_step_s": round(t_of, 4), "adjoint_step_s": round(t_oa, 4)}
     emit({"experiment": "adjoint", "workload": f"pbb_box {n_edge}^3", "n_fluid": n, "steps": T,
           "checkpoint_every": k, "J_mean_ux": float(J), "forward_s": round(t_fwd, 4),
           "backward_s": round(t_bwd, 4), "backward_over_forward": round(t_bwd / t_fwd, 2),
@@ -164,6 +217,7 @@ def adjoint(a):
           "fd_by_h": {str(h): {"max": float(v.max()), "median": float(np.median(v)),
                                "pass_1e-6": int((v <= 1e-6).sum())} for h, v in per_h.items()},
           "grad_abs_median": float(np.median(np.abs(g32))), "fd_seconds": round(t_fd, 1),
+          "cpu_baseline": cpu,
           "cells": [{"cell": int(c), "ns": float(ns_host[c]), "adjoint": float(g32[i]),
                      **{f"fd_{h:g}": float(fds[h][i]) for h in hs}} for i, c in enumerate(cells)]})
 
@@ -176,9 +230,11 @@ def batched(a):
     geoms = I.batch_packings(count=count)
     flags = [dev_flags(g) for g in geoms]
     steps = 200
+    from paper_1111_1129_amd.tune import tune_batch_layout
     for storage in ("f32", "f32s"):
-        batch = L.Batch(flags, [g.periodic for g in geoms], "lex")
-        prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), storage)
+        S, nt, chunk, _tab = tune_batch_layout(flags, [g.periodic for g in geoms], "lex", 0, storage)
+        batch = L.Batch(flags, [g.periodic for g in geoms], "lex", stride=S)
+        prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), storage, nontemporal=nt, xcd_chunk=chunk)
         tot_n = batch.total
         st = batch.init(prm)
         L.step(st, 2)
@@ -200,7 +256,24 @@ def batched(a):
 
         t_sep, _ = timed(separate)
         _, _, tot = L.moments(st, fields=False, segments=batch.segments)
+        cpu = None
+        if storage == "f32":
+            import oracle as O
+            oprm = O.TRT(0.8, 3 / 16, (1e-6, 0.0, 0.0))
+            t_cpu, cells = 0.0, 0
+            for g in geoms:
+                osp = O.build(g.flags, g.periodic, "lex")
+                of = O.init(osp.n_fluid)
+                og = np.empty_like(of)
+                t0 = time.perf_counter()
+                O.step(oprm, osp.adj, of, og)
+                t_cpu += time.perf_counter() - t0
+                cells += osp.n_fluid
+            cpu = {"value": round(cells / t_cpu / 1e6, 2), "unit": "MFLUPS",
+                   "cores": O.max_threads(), "kind": "oracle",
+                   "sample": "one FP64 sweep of every member geometry"}
         emit({"experiment": "batched", "geometries": count, "n_fluid_total": tot_n,
+              "cpu_baseline": cpu, "layout": [S, nt, chunk],
               "edge_min": min(g.dims[0] for g in geoms), "edge_max": max(g.dims[0] for g in geoms),
               "storage": storage, "steps": steps,
               "mflups_persistent": round(tot_n * steps / t_pers / 1e6, 1),

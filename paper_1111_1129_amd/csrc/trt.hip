@@ -26,9 +26,9 @@ constexpr int kBlock = 256;
 
 // persistent.hip
 constexpr size_t kPersistentWs = 256;
-lbm_status launch_persistent(int storage, const TrtConst& c, bool nt, int64_t n, int64_t stride,
-                             const uint32_t* adj, const double* ns, void* fa, void* fb,
-                             int n_steps, void* ws, hipStream_t s);
+lbm_status launch_persistent(int storage, const TrtConst& c, bool nt, int chunk_shift, int64_t n,
+                             int64_t stride, const uint32_t* adj, const double* ns, void* fa,
+                             void* fb, int n_steps, void* ws, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // init
@@ -104,7 +104,7 @@ lbm_status dispatch_step(const lbm_params& p, int64_t n, int64_t stride, const u
     const TrtConst c = make_trt_const(p);
     const bool nt = (p.flags & LBM_FLAG_NONTEMPORAL) != 0;
     const int cs = chunk_shift_for(p.flags, n, kBlock);
-    if (persistent) return launch_persistent(ST, c, nt, n, stride, adj, ns, fa, fb, n_steps, ws, s);
+    if (persistent) return launch_persistent(ST, c, nt, cs, n, stride, adj, ns, fa, fb, n_steps, ws, s);
     if (ns) return nt ? launch_steps<ST, true, true>(c, cs, n, stride, adj, ns, fa, fb, n_steps, s)
                       : launch_steps<ST, true, false>(c, cs, n, stride, adj, ns, fa, fb, n_steps, s);
     return nt ? launch_steps<ST, false, true>(c, cs, n, stride, adj, ns, fa, fb, n_steps, s)

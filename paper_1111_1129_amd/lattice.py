@@ -206,14 +206,15 @@ class Batch:
     carry its base, so one sweep over [0, sum N_k) advances all of them.
     """
 
-    def __init__(self, flags_list, periodic_list, order="lex", param=0, device="cuda"):
-        counts = []
-        for fl, per in zip(flags_list, periodic_list):
-            counts.append(count_fluid(fl, per, order, param))
-        self.counts = counts
+    def __init__(self, flags_list, periodic_list, order="lex", param=0, device="cuda",
+                 stride: int | None = None, counts=None):
+        if counts is None:
+            counts = [count_fluid(fl, per, order, param) for fl, per in zip(flags_list, periodic_list)]
+        self.counts = list(counts)
         self.bases = [sum(counts[:k]) for k in range(len(counts))]
         self.total = sum(counts)
-        self.stride = aligned_stride(self.total)
+        self.stride = aligned_stride(self.total) if stride is None else stride
+        assert self.stride >= self.total
         self.adj = torch.zeros((18, self.stride), dtype=torch.int32, device=device)
         self.lattices = []
         for fl, per, b in zip(flags_list, periodic_list, self.bases):

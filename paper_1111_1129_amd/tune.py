@@ -42,36 +42,53 @@ def candidate_strides(n: int) -> list[int]:
     return sorted(c for c in cands if c >= n)
 
 
+def _time_sweeps(lat, prm, sweeps, stream):
+    st = L.init(lat, prm)
+    L.step(st, 2)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    L.step(st, sweeps)
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / sweeps
+
+
 def tune_layout(flags: torch.Tensor, periodic: int, order: str = "lex", param: int = 0,
                 storage: str = "f64", force=(1e-6, 0.0, 0.0), sweeps: int = 6,
                 candidates: list[int] | None = None,
-                chunks: tuple = (1, 4, 16, 64, 0)) -> Layout:
-    """Time the candidate layouts on this geometry and return the fastest."""
+                chunks: tuple = (1, 4, 16, 64, 0), finalists: int = 4) -> Layout:
+    """Time the candidate layouts on this geometry and return the fastest.
+
+    Two stages: every candidate is timed over `sweeps` sweeps; the best
+    `finalists` are timed again, twice each and interleaved, over 3 x
+    `sweeps` sweeps, and the best mean wins (short timings alone are noisy
+    enough to mis-rank layouts a few percent apart)."""
     n = L.count_fluid(flags, periodic, order, param)
     cands = candidates or candidate_strides(n)
-    best = None
     table = []
     stream = torch.cuda.current_stream()
+    lats = {}
     for S in cands:
         lat = L.build(flags, periodic, order, param, stride=S)
         for nt in (False, True):
             for chunk in chunks:
                 prm = L.params(0.8, 3.0 / 16.0, force, storage, nontemporal=nt, xcd_chunk=chunk)
-                st = L.init(lat, prm)
-                L.step(st, 2)
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                L.step(st, sweeps)
-                e1.record(stream)
-                e1.synchronize()
-                t = e0.elapsed_time(e1) / 1e3 / sweeps
-                mflups = n / t / 1e6
-                table.append((S, nt, chunk, round(mflups, 1)))
-                if best is None or mflups > best.mflups:
-                    best = Layout(S, nt, chunk, mflups)
-                del st
+                t = _time_sweeps(lat, prm, sweeps, stream)
+                table.append((S, nt, chunk, round(n / t / 1e6, 1)))
         del lat
+    top = sorted(table, key=lambda r: -r[3])[:max(1, finalists)]
+    totals = {}
+    for _ in range(2):
+        for S, nt, chunk, _r in top:
+            if S not in lats:
+                lats.clear()
+                lats[S] = L.build(flags, periodic, order, param, stride=S)
+            prm = L.params(0.8, 3.0 / 16.0, force, storage, nontemporal=nt, xcd_chunk=chunk)
+            t = _time_sweeps(lats[S], prm, 3 * sweeps, stream)
+            totals[(S, nt, chunk)] = totals.get((S, nt, chunk), 0.0) + t
+    (S, nt, chunk), tsum = min(totals.items(), key=lambda kv: kv[1])
+    best = Layout(S, nt, chunk, n / (tsum / 2) / 1e6)
     best.table = table
     return best
 
@@ -117,3 +134,35 @@ def tune_ordering(flags: torch.Tensor, periodic: int, storage: str = "f64",
     if sample:  # re-tune the layout of the chosen ordering on the full geometry
         lay = tune_layout(flags, periodic, order, param, storage, force, sweeps=sweeps)
     return order, param, lay, table
+
+
+def tune_batch_layout(flags_list, periodic_list, order: str = "lex", param: int = 0,
+                      storage: str = "f32", force=(1e-6, 0.0, 0.0), sweeps: int = 6,
+                      chunks: tuple = (1, 16, 0)):
+    """Layout tuning for a Batch: candidate strides of the concatenated list x
+    {plain, nontemporal} x XCD chunk lengths, timed over one-launch-per-step
+    sweeps; returns (stride, nontemporal, xcd_chunk, table)."""
+    counts = [L.count_fluid(fl, per, order, param) for fl, per in zip(flags_list, periodic_list)]
+    total = sum(counts)
+    stream = torch.cuda.current_stream()
+    best, table = None, []
+    for S in candidate_strides(total):
+        batch = L.Batch(flags_list, periodic_list, order, param, stride=S, counts=counts)
+        for nt in (False, True):
+            for chunk in chunks:
+                prm = L.params(0.8, 3.0 / 16.0, force, storage, nontemporal=nt, xcd_chunk=chunk)
+                st = batch.init(prm)
+                L.step(st, 2)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                L.step(st, sweeps)
+                e1.record(stream)
+                e1.synchronize()
+                rate = total * sweeps / (e0.elapsed_time(e1) / 1e3) / 1e6
+                table.append((S, nt, chunk, round(rate, 1)))
+                if best is None or rate > best[3]:
+                    best = (S, nt, chunk, rate)
+                del st
+        del batch
+    return best[0], best[1], best[2], table
