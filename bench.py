@@ -17,7 +17,9 @@ bench_experiments.py): precision (FP64 / FP32 / shifted FP16 storage on the
 mean flux w.r.t. a partial-bounce-back field, checked against central
 differences), batched (64 uneven geometries, one persistent launch vs one
 launch per step vs separate launches), orderings (lexicographic, blocking
-factors, Z curves, random on the tube).
+factors, Z curves, random on the tube), partitions (neighbour chunks and
+remote links of a list cut into G chunks), ordering_tuner, compressed (sweep
+over 16-bit adjacency codes vs the full list).
 
 Besides the one JSON line the run reports, for the dominant kernel (the
 sweep), the achieved HBM bandwidth from its algorithmic bytes (19 PDFs read +
@@ -65,7 +67,7 @@ def parse():
                     help="consecutive tiles per XCD for --layout given (0 = one eighth each)")
     ap.add_argument("--experiment", default="headline",
                     choices=["headline", "precision", "adjoint", "batched", "orderings",
-                             "partitions", "ordering_tuner"],
+                             "partitions", "ordering_tuner", "compressed"],
                     help="headline: the JSON line below; the others print one JSON line per "
                          "configuration (see the module docstring)")
     ap.add_argument("--scale", type=int, default=1,

@@ -364,3 +364,64 @@ def ordering_tuner(a):
               "layout": [lay.stride, lay.nontemporal, lay.xcd_chunk],
               "full_geometry_mflups": round(lay.mflups, 1), "tuning_s": round(dt, 2),
               "candidates": table})
+
+
+# ---------------------------------------------------------------------------
+def c16_bytes(storage):
+    """Algorithmic bytes per cell update of the sweep over 16-bit codes:
+    19 loads + 19 stores of a PDF, 18 int16 codes, 18 int32 tile offsets per
+    256 cells."""
+    size = {"f64": 8, "f64s": 8, "f32": 4, "f32s": 4, "f16s": 2}[storage]
+    return 38 * size + 36 + 72 / 256
+
+
+def compressed(a):
+    """Sweep over 16-bit adjacency codes vs the full uint32 list: speed per
+    storage form and ordering, bitwise equality of the results."""
+    sweeps = 400
+    cases = [("tube_packing", I.packing_tube(2), "lex", 0),
+             ("tube_packing", I.packing_tube(2), "morton2", 0),
+             (f"large_packing/{a.scale}", I.workload("large_packing", scale=a.scale), "lex", 0)]
+    for name, g, order, param in cases:
+        flags = dev_flags(g)
+        for storage in ("f64", "f32s", "f16s"):
+            lay = tune_layout(flags, g.periodic, order, param, storage, sweeps=4)
+            lat = L.build(flags, g.periodic, order, param, stride=lay.stride)
+            n = lat.n_fluid
+            t_asm, comp = timed(lambda: L.compress(lat))
+            res = {}
+            for kind in ("full", "c16"):
+                best = None
+                for nt, chunk in ((lay.nontemporal, lay.xcd_chunk), (True, 1), (False, 1),
+                                  (True, 0), (False, 0)):
+                    prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), storage, nontemporal=nt,
+                                   xcd_chunk=chunk)
+                    st = L.init(lat, prm)
+                    if kind == "full":
+                        L.step(st, 2)
+                        st = L.init(lat, prm)
+                        t, _ = timed(lambda: L.step(st, sweeps))
+                    else:
+                        L.step_c16(st, comp, 2)
+                        st = L.init(lat, prm)
+                        t, _ = timed(lambda: L.step_c16(st, comp, sweeps))
+                    if best is None or t < best[0]:
+                        best = (t, nt, chunk, st.f[:, :n].clone())
+                    del st
+                res[kind] = best
+            same = bool(torch.equal(res["full"][3], res["c16"][3])) if \
+                res["full"][1:3] == res["c16"][1:3] else None
+            tf, tc = res["full"][0], res["c16"][0]
+            emit({"experiment": "compressed", "workload": name, "order": order, "n_fluid": n,
+                  "storage": storage, "sweeps": sweeps, "stride": lat.stride,
+                  "escapes": comp.n_escapes, "compress_ms": round(t_asm * 1e3, 2),
+                  "mflups_full": round(n * sweeps / tf / 1e6, 1),
+                  "mflups_c16": round(n * sweeps / tc / 1e6, 1),
+                  "speedup": round(tf / tc, 3),
+                  "layout_full": list(res["full"][1:3]), "layout_c16": list(res["c16"][1:3]),
+                  "gbs_full": round(BYTES[storage] * n * sweeps / tf / 1e9, 1),
+                  "gbs_c16": round(c16_bytes(storage) * n * sweeps / tc / 1e9, 1),
+                  "hbm_frac_c16": round(c16_bytes(storage) * n * sweeps / tc / 1e9 / PEAK, 4),
+                  "bitwise_equal": same})
+            del lat, comp, res
+            torch.cuda.empty_cache()

@@ -280,6 +280,53 @@ lbm_status lbm_partition_stats(int64_t n, int64_t stride, const uint32_t* adj, i
                                int32_t* interface_cells, void* workspace, size_t* ws_bytes,
                                void* stream);
 
+/*
+ * lbm_compress_adjacency -- 16-bit re-encoding of the adjacency list
+ * (byte reduction of the sweep over the sparse representation of Sec. 2,
+ * whose adjacency list is read by every pull update of Sec. 5: in FP64 it
+ * is 72 of the 376 bytes an update moves).
+ *
+ * List tiles are 256 consecutive cells.  Per tile t and direction i = k + 1
+ * an int32 offset o = tile_records[t * 20 + k] is chosen, and entry
+ * adj[k][m] = i * stride + src becomes the int16
+ *   codes[k * stride + m] = src - m - o
+ * when that lies in [-32766, 32767]; an implicit bounce-back entry
+ * (opp(i) * stride + m) becomes -32768, any other entry -32767 ("escape").
+ * tile_records[t * 20 + 18] = number of escapes in tile t, [t * 20 + 19] = 0.
+ * The encoding is lossless.
+ *
+ *  adj           uint32 [18][stride] from lbm_build_adjacency (input).
+ *  codes         int16  [18][stride] (output; columns >= n untouched).
+ *  tile_records  int32  [ceil(n / 256) * 20] (output).
+ *  n_escapes     (host) number of escape codes written.
+ *  workspace, ws_bytes  256 bytes of device scratch (query with workspace
+ *        NULL).  The call synchronizes the stream to return n_escapes.
+ * Errors: LBM_EINVAL (NULL pointers, n <= 0), LBM_EOVERFLOW, LBM_EWORKSPACE,
+ * LBM_EHIP.
+ */
+lbm_status lbm_compress_adjacency(int64_t n, int64_t stride, const uint32_t* adj, int16_t* codes,
+                                  int32_t* tile_records, int64_t* n_escapes, void* workspace,
+                                  size_t* ws_bytes, void* stream);
+
+/*
+ * lbm_step_c16 -- n_steps TRT pull sweeps (as lbm_step, one parameter set,
+ * one launch per step) reading the 16-bit codes of lbm_compress_adjacency:
+ * a tile without escapes moves 19 * 2 * sizeof(PDF) + 36.3 bytes per cell
+ * update instead of 19 * 2 * sizeof(PDF) + 72; a tile with escapes reads
+ * adj.  The gathered slots are the ones adj names, so results are bitwise
+ * equal to lbm_step's.
+ *
+ *  codes, tile_records  from lbm_compress_adjacency for the same n, stride
+ *        and adj (other codes can address memory outside f).
+ *  adj   the uncompressed list (read in tiles with escapes).
+ *  ns, f_a, f_b, n_steps, stream  as lbm_step (f_a: state in; the result is
+ *        in f_b after an odd, in f_a after an even number of steps).
+ * Errors: LBM_EINVAL, LBM_EOVERFLOW, LBM_EHIP.
+ */
+lbm_status lbm_step_c16(const lbm_params* p, int64_t n, int64_t stride, const int16_t* codes,
+                        const int32_t* tile_records, const uint32_t* adj, const double* ns,
+                        void* f_a, void* f_b, int32_t n_steps, void* stream);
+
 /* Library version (major*10000 + minor*100 + patch) and a static string for a
  * status code.  Both are host-only and allocate nothing. */
 int32_t lbm_version(void);

@@ -17,7 +17,8 @@ from .inputs import Geometry  # noqa: F401  (seeded synthetic inputs)
 def __getattr__(name):
     # lazy: keep `import paper_1111_1129_amd.inputs` free of torch and HIP
     if name in ("build", "init", "step", "moments", "params", "set_state", "count_fluid",
-                "partition_stats", "aligned_stride", "Lattice", "State", "Batch"):
+                "partition_stats", "aligned_stride", "Lattice", "State", "Batch",
+                "compress", "step_c16", "Compressed"):
         from . import lattice
         return getattr(lattice, name)
     if name in ("PermeabilityFn", "adjoint_gradient", "forward_states"):
@@ -27,7 +28,8 @@ def __getattr__(name):
         from . import tune
         return getattr(tune, name)
     if name in ("lbm_build_adjacency", "lbm_init", "lbm_step", "lbm_step_adjoint", "lbm_moments",
-                "lbm_partition_stats", "lbm_version", "LbmError"):
+                "lbm_partition_stats", "lbm_compress_adjacency", "lbm_step_c16", "lbm_version",
+                "LbmError"):
         from . import _native
         return getattr(_native, name)
     raise AttributeError(name)

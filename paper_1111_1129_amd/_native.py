@@ -26,7 +26,8 @@ FLAG_NONTEMPORAL = 1
 FLAG_XCD_CHUNK_SHIFT = 8
 
 ENTRY_POINTS = ("lbm_build_adjacency", "lbm_init", "lbm_step", "lbm_step_adjoint",
-                "lbm_moments", "lbm_partition_stats", "lbm_version", "lbm_status_string")
+                "lbm_moments", "lbm_partition_stats", "lbm_compress_adjacency", "lbm_step_c16",
+                "lbm_version", "lbm_status_string")
 
 
 class lbm_geom(C.Structure):
@@ -81,6 +82,11 @@ def load(path: str = LIB_PATH):
                                     C.POINTER(SZ), P]
         lib.lbm_partition_stats.restype = I32
         lib.lbm_partition_stats.argtypes = [I64, I64, P, I64, P, P, P, P, C.POINTER(SZ), P]
+        lib.lbm_compress_adjacency.restype = I32
+        lib.lbm_compress_adjacency.argtypes = [I64, I64, P, P, P, C.POINTER(C.c_int64), P,
+                                               C.POINTER(SZ), P]
+        lib.lbm_step_c16.restype = I32
+        lib.lbm_step_c16.argtypes = [C.POINTER(lbm_params), I64, I64, P, P, P, P, P, P, I32, P]
         lib.lbm_version.restype = I32
         lib.lbm_version.argtypes = []
         lib.lbm_status_string.restype = C.c_char_p
@@ -189,6 +195,25 @@ def lbm_partition_stats(n, stride, adj, n_chunks, remote_links, neighbours, inte
                                  None if query else _ptr(workspace), C.byref(ws),
                                  None if query else _stream(stream))
     return st, ws.value
+
+
+def lbm_compress_adjacency(n, stride, adj, codes, tile_records, workspace=None, ws_bytes=0,
+                           stream=None, query=False):
+    """Returns (status, n_escapes, ws_bytes).  Synchronizes the stream."""
+    lib = load()
+    ws = C.c_size_t(ws_bytes)
+    esc = C.c_int64(0)
+    st = lib.lbm_compress_adjacency(n, stride, _ptr(adj), _ptr(codes), _ptr(tile_records),
+                                    C.byref(esc), None if query else _ptr(workspace),
+                                    C.byref(ws), None if query else _stream(stream))
+    return st, esc.value, ws.value
+
+
+def lbm_step_c16(params: lbm_params, n, stride, codes, tile_records, adj, ns, f_a, f_b, n_steps,
+                 stream=None):
+    return load().lbm_step_c16(C.byref(params), n, stride, _ptr(codes), _ptr(tile_records),
+                               _ptr(adj), _ptr(ns), _ptr(f_a), _ptr(f_b), int(n_steps),
+                               _stream(stream))
 
 
 def lbm_version() -> int:

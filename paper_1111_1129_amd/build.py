@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB_PATH = os.path.join(PKG, "liblbm.so")
 SOURCES = ["assembly.hip", "trt.hip", "persistent.hip", "moments.hip", "adjoint.hip",
-           "partition.hip", "abi.cpp"]
+           "partition.hip", "compress.hip", "abi.cpp"]
 ARCH = "gfx950"
 
 
@@ -34,6 +34,11 @@ def compile_flags() -> list[str]:
     return [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
             # packed FP32 instructions are kept out of every kernel
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            # a*b+c is fused only inside one source expression: which products
+            # the compiler fuses then does not depend on the code around the
+            # collision, so every kernel that inlines it (one launch per step,
+            # persistent, 16-bit codes) rounds identically
+            "-ffp-contract=on",
             f"-I{INCLUDE}", f"-I{CSRC}"]
 
 

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <type_traits>
 
 #include "lbm.h"
 
@@ -43,8 +44,13 @@ template <> struct Storage<LBM_F32_SHIFTED> { using T = float; using A = float; 
 template <> struct Storage<LBM_F16_SHIFTED> { using T = _Float16; using A = float; static constexpr bool shifted = true; };
 
 template <class T, class A> __device__ __forceinline__ A ld(const T* p) { return static_cast<A>(*p); }
-// FP32 -> FP16 conversion rounds to nearest even (IEEE default mode)
+// FP32 -> FP16 conversion rounds to nearest even (IEEE default mode).  The
+// value is first rounded to A: the empty asm hides how it was computed, so the
+// compiler cannot fold the conversion into a mixed-precision FMA that rounds
+// an unrounded product-sum straight to FP16 (it does so in some kernels and
+// not in others, which would make their results differ in the last bit).
 template <class T, class A, bool NT> __device__ __forceinline__ void st(T* p, A v) {
+    if constexpr (!std::is_same_v<T, A>) asm("" : "+v"(v));
     if constexpr (NT)
         __builtin_nontemporal_store(static_cast<T>(v), p);
     else

@@ -199,6 +199,43 @@ def partition_stats(lat: Lattice, n_chunks: int, n: int | None = None, stream=No
     return remote, nb, iface
 
 
+@dataclasses.dataclass
+class Compressed:
+    """16-bit adjacency codes of a lattice (lbm_compress_adjacency)."""
+
+    codes: torch.Tensor         # int16 [18][stride]
+    tile_records: torch.Tensor  # int32 [ceil(n / 256)][20]: 18 offsets, escapes, 0
+    n: int
+    n_escapes: int
+
+
+def compress(lat: Lattice, n: int | None = None, stream=None) -> Compressed:
+    """Re-encode adj[:, :n] as int16 offsets from per-tile bases (lossless)."""
+    n = lat.base + lat.n_fluid if n is None else n
+    dev = lat.device
+    codes = torch.empty((18, lat.stride), dtype=torch.int16, device=dev)
+    toff = torch.empty(((n + 255) // 256, 20), dtype=torch.int32, device=dev)
+    st, _, wsn = N.lbm_compress_adjacency(n, lat.stride, lat.adj, codes, toff, query=True)
+    N._check("lbm_compress_adjacency", st)
+    ws = torch.empty(wsn, dtype=torch.uint8, device=dev)
+    st, esc, _ = N.lbm_compress_adjacency(n, lat.stride, lat.adj, codes, toff, ws, wsn, stream)
+    N._check("lbm_compress_adjacency", st)
+    return Compressed(codes, toff, n, esc)
+
+
+def step_c16(state: State, comp: Compressed, n_steps: int = 1, stream=None):
+    """As step(), reading the 16-bit codes (results bitwise equal)."""
+    lat = state.lattice
+    assert comp.n == state.n and comp.codes.shape[1] == lat.stride
+    st = N.lbm_step_c16(state.params, state.n, lat.stride, comp.codes, comp.tile_records, lat.adj,
+                        state.ns, state.f, state.g, n_steps, stream)
+    N._check("lbm_step_c16", st)
+    if n_steps % 2 == 1:
+        state.f, state.g = state.g, state.f
+    state.steps += n_steps
+    return state
+
+
 class Batch:
     """Many geometries in one set of [19][S] / [18][S] arrays.
 

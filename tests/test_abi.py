@@ -118,3 +118,44 @@ def test_host_side_argument_errors(lib):
     f32 = N.make_params(0.8, 3 / 16, storage="f32")
     assert lib.lbm_step_adjoint(C.byref(f32), 10, 10, dummy, dummy, None, dummy, dummy, None,
                                 None) == N.LBM_EINVAL
+
+
+def test_compressed_adjacency_argument_errors(lib):
+    from paper_1111_1129_amd import _native as N
+    P = C.c_void_p
+    lib.lbm_compress_adjacency.restype = C.c_int32
+    lib.lbm_compress_adjacency.argtypes = [C.c_int64, C.c_int64, P, P, P, C.POINTER(C.c_int64),
+                                           P, C.POINTER(C.c_size_t), P]
+    esc = C.c_int64(0)
+    ws = C.c_size_t(0)
+    assert lib.lbm_compress_adjacency(10, 10, None, None, None, C.byref(esc), None, C.byref(ws),
+                                      None) == N.LBM_OK and ws.value == 256
+    assert lib.lbm_compress_adjacency(10, 10, None, None, None, C.byref(esc), None, None,
+                                      None) == N.LBM_EINVAL
+    small = C.c_size_t(8)
+    assert lib.lbm_compress_adjacency(10, 10, P(4096), P(4096), P(4096), C.byref(esc), P(4096),
+                                      C.byref(small), None) == N.LBM_EWORKSPACE
+    ok = C.c_size_t(256)
+    assert lib.lbm_compress_adjacency(10, 5, P(4096), P(4096), P(4096), C.byref(esc), P(4096),
+                                      C.byref(ok), None) == N.LBM_EINVAL       # stride < n
+    assert lib.lbm_compress_adjacency(0, 5, P(4096), P(4096), P(4096), C.byref(esc), P(4096),
+                                      C.byref(ok), None) == N.LBM_EINVAL       # empty list
+    assert lib.lbm_compress_adjacency(10, 10, None, P(4096), P(4096), C.byref(esc), P(4096),
+                                      C.byref(ok), None) == N.LBM_EINVAL
+
+    lib.lbm_step_c16.restype = C.c_int32
+    lib.lbm_step_c16.argtypes = [C.POINTER(N.lbm_params), C.c_int64, C.c_int64, P, P, P, P, P, P,
+                                 C.c_int32, P]
+    good = N.make_params(0.8, 3 / 16, (1e-6, 0, 0), "f64")
+    d = P(4096)
+
+    def step(p=good, n=10, stride=10, codes=d, a=d, b=P(8192), steps=1):
+        return lib.lbm_step_c16(C.byref(p), n, stride, codes, d, d, None, a, b, steps, None)
+
+    assert step(p=N.make_params(0.5, 3 / 16)) == N.LBM_EINVAL
+    assert step(codes=None) == N.LBM_EINVAL
+    assert step(b=d) == N.LBM_EINVAL                   # in place
+    assert step(stride=5) == N.LBM_EINVAL
+    assert step(steps=-1) == N.LBM_EINVAL
+    assert step(stride=(1 << 32) // 19 + 1) == N.LBM_EOVERFLOW
+    assert step(steps=0) == N.LBM_OK                  # nothing to do, nothing launched
