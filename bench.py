@@ -10,6 +10,10 @@ whole job (MFLUPS, counting fluid cells only).
 Default workload: 256^3 tube (diameter 240) packed with radius-12 spheres by
 seeded random sequential addition, periodic in x, force-driven, D3Q19 TRT with
 tau+ = 0.8, magic 3/16, 1000 sweeps, FP64 storage, lexicographic ordering.
+The sweep reads the adjacency as 16-bit codes (``--sweep c16``: the codes are
+built inside the step; results are bitwise those of the sweep over the full
+uint32 list, ``--sweep full``); ``inplace`` / ``inplace_c16`` step one PDF
+array instead of two.
 
 Experiments (``--experiment``, one JSON line per configuration, see
 bench_experiments.py): precision (FP64 / FP32 / shifted FP16 storage on the
@@ -23,9 +27,10 @@ over 16-bit adjacency codes vs the full list).
 
 Besides the one JSON line the run reports, for the dominant kernel (the
 sweep), the achieved HBM bandwidth from its algorithmic bytes (19 PDFs read +
-19 written + 18 uint32 adjacency entries per fluid cell) and its average
-launch time measured with HIP events on the launch stream, and a CPU baseline:
-the plain FP64 oracle timed on the host cores on a bounded sample.
+19 written + the adjacency: 18 uint32 entries, or 18 int16 codes and an
+80-byte record per 256 cells, per fluid cell) and its average launch time
+measured with HIP events on the launch stream, and a CPU baseline: the plain
+FP64 oracle timed on the host cores on a bounded sample.
 """
 from __future__ import annotations
 
@@ -43,7 +48,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 METRIC = "MFLUPS and % of HBM peak, D3Q19 TRT sparse sweep; FP64 vs FP32/FP16 at stated error"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_FLUP = {"f64": 376, "f64s": 376, "f32": 224, "f32s": 224, "f16s": 148}
-KERNEL_SOURCES = ["paper_1111_1129_amd/csrc/trt.hip", "paper_1111_1129_amd/csrc/lbm_device.hpp"]
+PDF_SIZE = {"f64": 8, "f64s": 8, "f32": 4, "f32s": 4, "f16s": 2}
+SWEEP_KERNELS = {"full": ("k_trt", "trt.hip"), "c16": ("k_trt_c16", "compress.hip"),
+                 "inplace": ("k_gather_scatter + k_local", "inplace.hip"),
+                 "inplace_c16": ("k_gather_scatter + k_local", "inplace.hip")}
+
+
+def sweep_bytes(storage: str, kind: str) -> float:
+    """Algorithmic bytes per cell update: 19 PDF loads + 19 stores, plus the
+    adjacency: 18 uint32 (full list) or 18 int16 codes + an 80-byte tile
+    record per 256 cells (c16); the in-place sweep reads it every other step."""
+    adj = 36 + 80 / 256 if kind.endswith("c16") else 72.0
+    if kind.startswith("inplace"):
+        adj /= 2
+    return 38 * PDF_SIZE[storage] + adj
+
+
+def kernel_sources(kind: str):
+    return ["paper_1111_1129_amd/csrc/" + SWEEP_KERNELS[kind][1],
+            "paper_1111_1129_amd/csrc/lbm_device.hpp"]
 
 
 def parse():
@@ -57,6 +80,9 @@ def parse():
     ap.add_argument("--order", default="lex")
     ap.add_argument("--param", type=int, default=0)
     ap.add_argument("--storage", default="f64", choices=list(BYTES_PER_FLUP))
+    ap.add_argument("--sweep", default="c16", choices=list(SWEEP_KERNELS),
+                    help="full: two arrays, uint32 adjacency; c16: two arrays, 16-bit codes; "
+                         "inplace / inplace_c16: one PDF array")
     ap.add_argument("--layout", default="tuned", choices=["tuned", "aligned", "given"],
                     help="tuned: time candidate row strides / store policies on the geometry "
                          "first (excluded from the timed region); aligned: 128-byte aligned "
@@ -77,24 +103,28 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(kind: str) -> str:
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in kernel_sources(kind):
         with open(os.path.join(ROOT, rel), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(workload: str, order: str, storage: str):
+def profile_name(kind: str, storage: str, workload: str, order: str, what: str) -> str:
+    return os.path.join(ROOT, "profiles", f"sweep_{kind}_{storage}_{workload}_{order}_{what}.txt")
+
+
+def traffic_from_profile(kind: str, workload: str, order: str, storage: str):
     """HBM bytes per sweep launch from the committed PMC summary, if it was
     taken on the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", f"trt_{storage}_{workload}_{order}_pmc.txt")
+    path = profile_name(kind, storage, workload, order, "pmc")
     if not os.path.exists(path):
         return None
     text = open(path).read()
     m_hash = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
     m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash():
+    if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash(kind):
         return None
     return float(m_bytes.group(1))
 
@@ -154,7 +184,7 @@ def main():
     flags = torch.from_numpy(np.ascontiguousarray(geom.flags)).to(dev)
     if a.layout == "tuned":
         from paper_1111_1129_amd.tune import tune_layout
-        lay = tune_layout(flags, geom.periodic, a.order, a.param, a.storage)
+        lay = tune_layout(flags, geom.periodic, a.order, a.param, a.storage, sweep=a.sweep)
         stride, nt, chunk = lay.stride, lay.nontemporal, lay.xcd_chunk
         for row in lay.table:
             print("tune stride=%d nt=%d chunk=%d: %.0f MFLUPS" % row, file=sys.stderr)
@@ -164,13 +194,18 @@ def main():
         stride, nt, chunk = None, False, 0
     prm = L.params(0.8, 3.0 / 16.0, (1e-6, 0.0, 0.0), a.storage, nontemporal=nt, xcd_chunk=chunk)
     stream = torch.cuda.current_stream()
+    from paper_1111_1129_amd.tune import Sweeper
+    if a.sweep.startswith("inplace") and a.sweeps % 2:
+        print(json.dumps({"error": "the in-place sweep needs an even --sweeps"}))
+        sys.exit(2)
 
     def one_pass(ev=None):
         lat = L.build(flags, geom.periodic, a.order, a.param, stride=stride)
-        st = L.init(lat, prm)
+        sw = Sweeper(lat, a.sweep)  # builds the 16-bit codes for the c16 kinds
+        st = sw.init(prm)
         if ev is not None:
             ev[0].record(stream)
-        L.step(st, a.sweeps)
+        sw.step(st, a.sweeps)
         if ev is not None:
             ev[1].record(stream)
         _, _, totals = L.moments(st, fields=False)
@@ -197,7 +232,7 @@ def main():
 
     flups = n_fluid * a.sweeps * a.steps
     value = flups / wall / 1e6
-    bpf = BYTES_PER_FLUP[a.storage]
+    bpf = sweep_bytes(a.storage, a.sweep)
     achieved = bpf * n_fluid / launch_s / 1e9
     line = {
         "metric": METRIC,
@@ -214,13 +249,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{a.workload}: {desc}", "n_fluid": n_fluid,
                    "sweeps_per_step": a.sweeps, "order": a.order, "order_param": a.param,
-                   "storage": a.storage, "tau_plus": 0.8, "magic": 0.1875, "force_x": 1e-6,
+                   "storage": a.storage, "sweep": a.sweep,
+                   "tau_plus": 0.8, "magic": 0.1875, "force_x": 1e-6,
                    "layout": a.layout, "row_stride": lat.stride, "nontemporal": nt,
                    "xcd_chunk": chunk},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic_from_profile(a.workload, a.order, a.storage),
-                     "kernel": "k_trt (one sweep launch)", "bytes_per_flup": bpf,
+                     "traffic": traffic_from_profile(a.sweep, a.workload, a.order, a.storage),
+                     "kernel": SWEEP_KERNELS[a.sweep][0] + " (one sweep launch)",
+                     "bytes_per_flup": round(bpf, 2),
                      "sweep_mflups": round(n_fluid / launch_s / 1e6, 1),
                      "avg_launch_us": round(launch_s * 1e6, 2)},
         "cpu_baseline": None,

@@ -19,6 +19,8 @@ from paper_1111_1129_amd import inputs as I
 from paper_1111_1129_amd import lattice as L
 from paper_1111_1129_amd.tune import tune_layout, tune_ordering, candidate_strides
 
+from bench import PDF_SIZE, sweep_bytes  # one definition of the per-update byte counts
+
 BYTES = {"f64": 376, "f64s": 376, "f32": 224, "f32s": 224, "f16s": 148}
 PEAK = 8000.0
 
@@ -367,18 +369,19 @@ def ordering_tuner(a):
 
 
 # ---------------------------------------------------------------------------
-def c16_bytes(storage):
-    """Algorithmic bytes per cell update of the sweep over 16-bit codes:
-    19 loads + 19 stores of a PDF, 18 int16 codes, 18 int32 tile offsets per
-    256 cells."""
-    size = {"f64": 8, "f64s": 8, "f32": 4, "f32s": 4, "f16s": 2}[storage]
-    return 38 * size + 36 + 72 / 256
+def bytes_resident(storage, kind):
+    """HBM bytes per cell held by the arrays a sweep needs."""
+    pdf = 19 * PDF_SIZE[storage] * (1 if kind.startswith("inplace") else 2)
+    return pdf + 72 + (36 if "c16" in kind else 0)
 
 
 def compressed(a):
-    """Sweep over 16-bit adjacency codes vs the full uint32 list: speed per
-    storage form and ordering, bitwise equality of the results."""
+    """Byte reduction: the sweep over 16-bit adjacency codes and the in-place
+    sweep (one PDF array), each against the two-array sweep over the full
+    uint32 list: speed per storage form and ordering, bitwise equality of the
+    results after the same (even) number of sweeps."""
     sweeps = 400
+    kinds = ("full", "c16", "inplace", "inplace_c16")
     cases = [("tube_packing", I.packing_tube(2), "lex", 0),
              ("tube_packing", I.packing_tube(2), "morton2", 0),
              (f"large_packing/{a.scale}", I.workload("large_packing", scale=a.scale), "lex", 0)]
@@ -390,38 +393,44 @@ def compressed(a):
             n = lat.n_fluid
             t_asm, comp = timed(lambda: L.compress(lat))
             res = {}
-            for kind in ("full", "c16"):
+            for kind in kinds:
                 best = None
                 for nt, chunk in ((lay.nontemporal, lay.xcd_chunk), (True, 1), (False, 1),
                                   (True, 0), (False, 0)):
                     prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), storage, nontemporal=nt,
                                    xcd_chunk=chunk)
-                    st = L.init(lat, prm)
-                    if kind == "full":
-                        L.step(st, 2)
-                        st = L.init(lat, prm)
-                        t, _ = timed(lambda: L.step(st, sweeps))
+                    if kind in ("full", "c16"):
+                        def run(k, st):
+                            return L.step(st, k) if kind == "full" else L.step_c16(st, comp, k)
+                        make = L.init
                     else:
-                        L.step_c16(st, comp, 2)
-                        st = L.init(lat, prm)
-                        t, _ = timed(lambda: L.step_c16(st, comp, sweeps))
+                        def run(k, st):
+                            return L.step_inplace(st, k, comp if kind == "inplace_c16" else None)
+                        make = L.init_inplace
+                    st = make(lat, prm)
+                    run(2, st)
+                    st = make(lat, prm)
+                    t, _ = timed(lambda: run(sweeps, st))
                     if best is None or t < best[0]:
                         best = (t, nt, chunk, st.f[:, :n].clone())
                     del st
+                    torch.cuda.empty_cache()
                 res[kind] = best
-            same = bool(torch.equal(res["full"][3], res["c16"][3])) if \
-                res["full"][1:3] == res["c16"][1:3] else None
-            tf, tc = res["full"][0], res["c16"][0]
-            emit({"experiment": "compressed", "workload": name, "order": order, "n_fluid": n,
-                  "storage": storage, "sweeps": sweeps, "stride": lat.stride,
-                  "escapes": comp.n_escapes, "compress_ms": round(t_asm * 1e3, 2),
-                  "mflups_full": round(n * sweeps / tf / 1e6, 1),
-                  "mflups_c16": round(n * sweeps / tc / 1e6, 1),
-                  "speedup": round(tf / tc, 3),
-                  "layout_full": list(res["full"][1:3]), "layout_c16": list(res["c16"][1:3]),
-                  "gbs_full": round(BYTES[storage] * n * sweeps / tf / 1e9, 1),
-                  "gbs_c16": round(c16_bytes(storage) * n * sweeps / tc / 1e9, 1),
-                  "hbm_frac_c16": round(c16_bytes(storage) * n * sweeps / tc / 1e9 / PEAK, 4),
-                  "bitwise_equal": same})
+            tf = res["full"][0]
+            rec = {"experiment": "compressed", "workload": name, "order": order, "n_fluid": n,
+                   "storage": storage, "sweeps": sweeps, "stride": lat.stride,
+                   "escapes": comp.n_escapes, "compress_ms": round(t_asm * 1e3, 2)}
+            for kind in kinds:
+                t, nt, chunk, f = res[kind]
+                rec[kind] = {"mflups": round(n * sweeps / t / 1e6, 1),
+                             "speedup": round(tf / t, 3),
+                             "bytes_per_update": round(sweep_bytes(storage, kind), 2),
+                             "gbs": round(sweep_bytes(storage, kind) * n * sweeps / t / 1e9, 1),
+                             "hbm_frac": round(sweep_bytes(storage, kind) * n * sweeps / t / 1e9
+                                               / PEAK, 4),
+                             "resident_bytes_per_cell": bytes_resident(storage, kind),
+                             "layout": [nt, chunk],
+                             "bitwise_equal_full": bool(torch.equal(f, res["full"][3]))}
+            emit(rec)
             del lat, comp, res
             torch.cuda.empty_cache()

@@ -327,6 +327,39 @@ lbm_status lbm_step_c16(const lbm_params* p, int64_t n, int64_t stride, const in
                         const int32_t* tile_records, const uint32_t* adj, const double* ns,
                         void* f_a, void* f_b, int32_t n_steps, void* stream);
 
+/*
+ * lbm_step_inplace -- n_steps TRT pull sweeps on ONE PDF array (halves the
+ * PDF memory of lbm_step's two arrays; the sweep of Sec. 5 on the sparse
+ * representation of Sec. 2).
+ *
+ * Two kinds of step alternate.  Phase 0 ("layout P", the layout lbm_init and
+ * lbm_step produce: slot (i, m) holds the post-collision f*_i of cell m):
+ * each cell gathers through adj as lbm_step does, collides, and stores out_i
+ * into the slot it gathered direction opp(i) from.  Phase 1 ("layout Q":
+ * slot (opp(i), m) holds the population arriving at m in direction i): each
+ * cell reads its own column with rows swapped, collides and stores out_i to
+ * (i, m).  Each cell reads and writes the same 19 slots, so a step is safe in
+ * place.  After an even number of steps from phase 0 the array is bitwise
+ * what lbm_step gives; a tile of 256 cells moves 19 * 2 PDFs per step and
+ * reads the adjacency only in phase-0 steps.
+ *
+ *  adj       the pull adjacency of lbm_build_adjacency.  The n listed cells
+ *            must hold whole geometries: every slot adj names for m < n is a
+ *            slot of a cell < n.
+ *  codes, tile_records  16-bit codes of lbm_compress_adjacency for the same
+ *            n, stride and adj (read instead of adj in phase-0 steps), or
+ *            both NULL.
+ *  ns        PBB solid fraction [stride] or NULL.
+ *  f         [19][stride] state in layout `phase`; on return it is in layout
+ *            (phase + n_steps) % 2.  lbm_moments and lbm_step expect layout P.
+ *  phase     0 or 1.
+ * Errors: LBM_EINVAL (bad params, NULL adj/f, phase not 0/1, only one of
+ * codes and tile_records given), LBM_EOVERFLOW, LBM_EHIP.
+ */
+lbm_status lbm_step_inplace(const lbm_params* p, int64_t n, int64_t stride, const uint32_t* adj,
+                            const int16_t* codes, const int32_t* tile_records, const double* ns,
+                            void* f, int32_t phase, int32_t n_steps, void* stream);
+
 /* Library version (major*10000 + minor*100 + patch) and a static string for a
  * status code.  Both are host-only and allocate nothing. */
 int32_t lbm_version(void);

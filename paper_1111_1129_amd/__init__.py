@@ -18,7 +18,8 @@ def __getattr__(name):
     # lazy: keep `import paper_1111_1129_amd.inputs` free of torch and HIP
     if name in ("build", "init", "step", "moments", "params", "set_state", "count_fluid",
                 "partition_stats", "aligned_stride", "Lattice", "State", "Batch",
-                "compress", "step_c16", "Compressed"):
+                "compress", "step_c16", "Compressed", "InplaceState", "init_inplace",
+                "step_inplace"):
         from . import lattice
         return getattr(lattice, name)
     if name in ("PermeabilityFn", "adjoint_gradient", "forward_states"):
@@ -28,7 +29,8 @@ def __getattr__(name):
         from . import tune
         return getattr(tune, name)
     if name in ("lbm_build_adjacency", "lbm_init", "lbm_step", "lbm_step_adjoint", "lbm_moments",
-                "lbm_partition_stats", "lbm_compress_adjacency", "lbm_step_c16", "lbm_version",
+                "lbm_partition_stats", "lbm_compress_adjacency", "lbm_step_c16",
+                "lbm_step_inplace", "lbm_version",
                 "LbmError"):
         from . import _native
         return getattr(_native, name)

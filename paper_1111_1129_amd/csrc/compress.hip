@@ -24,12 +24,8 @@
 
 namespace lbm {
 
-constexpr int kCTile = 256;  // cells per tile = workgroup size of the sweep
-constexpr int kRec = 20;     // int32 words per tile record: 18 offsets, escapes, 0
-constexpr int16_t kBounce = -32768;
-constexpr int16_t kEscape = -32767;
-constexpr int32_t kMinCode = -32766;  // codes kMinCode..kMaxCode are offsets
-constexpr int32_t kMaxCode = 32767;
+constexpr int kCTile = kCodeTile;  // cells per tile = workgroup size of the sweep
+constexpr int kRec = kCodeRec;
 
 __global__ __launch_bounds__(kCTile) void k_compress(const uint32_t* __restrict__ adj, int64_t n,
                                                      int64_t stride, int16_t* __restrict__ codes,
@@ -69,11 +65,11 @@ __global__ __launch_bounds__(kCTile) void k_compress(const uint32_t* __restrict_
         if (live) {
             int16_t c;
             if (!streams) {
-                c = kBounce;
-            } else if (d - base >= kMinCode && d - base <= kMaxCode) {
+                c = kCodeBounce;
+            } else if (d - base >= kCodeMin && d - base <= kCodeMax) {
                 c = int16_t(d - base);
             } else {
-                c = kEscape;
+                c = kCodeEscape;
                 ++esc;
             }
             codes[k * stride + m] = c;
@@ -117,7 +113,7 @@ __device__ __forceinline__ void update_cell_c16(const typename Storage<ST>::T* _
         const uint32_t i = k + 1;
         const uint32_t streamed = i * S + uint32_t(rec[k]) + mm + uint32_t(cd[k]);
         const uint32_t bounced = uint32_t(opp(int(i))) * S + mm;
-        g[i] = ld<T, A>(src + (cd[k] == kBounce ? bounced : streamed));
+        g[i] = ld<T, A>(src + (cd[k] == kCodeBounce ? bounced : streamed));
     }
     A sf = A(0);
     if constexpr (PBB) sf = static_cast<A>(ns[m]);

@@ -66,6 +66,16 @@ inline size_t storage_bytes(int st) {
     }
 }
 
+// 16-bit adjacency codes (lbm_compress_adjacency): tiles of 256 list cells,
+// one record of 20 int32 words per tile (18 direction offsets, the number of
+// escape codes in the tile, a zero word); reserved code values.
+constexpr int kCodeTile = 256;
+constexpr int kCodeRec = 20;
+constexpr int16_t kCodeBounce = -32768;
+constexpr int16_t kCodeEscape = -32767;
+constexpr int32_t kCodeMin = -32766;
+constexpr int32_t kCodeMax = 32767;
+
 // ---------------------------------------------------------------------------
 // TRT constants of one launch (host-computed in FP64).
 // ---------------------------------------------------------------------------

@@ -164,6 +164,7 @@ def step(state: State, n_steps: int = 1, persistent: bool = False, segments=None
 
 def moments(state: State, fields: bool = True, segments=None, stream=None):
     """(rho [n], u [3][n], totals [n_seg or 1][4]) in FP64 on the device."""
+    assert getattr(state, "phase", 0) == 0, "in-place state must be in phase 0 (an even step count)"
     lat = state.lattice
     n = state.n
     dev = lat.device
@@ -232,6 +233,49 @@ def step_c16(state: State, comp: Compressed, n_steps: int = 1, stream=None):
     N._check("lbm_step_c16", st)
     if n_steps % 2 == 1:
         state.f, state.g = state.g, state.f
+    state.steps += n_steps
+    return state
+
+
+@dataclasses.dataclass
+class InplaceState:
+    """One PDF array [19][stride] stepped in place (lbm_step_inplace).
+
+    phase 0: slot (i, m) holds the post-collision f*_i(m), the layout of
+    State.f (moments() and step() expect it); phase 1: slot (opp(i), m) holds
+    the population arriving at m in direction i."""
+
+    lattice: Lattice
+    params: N.lbm_params
+    f: torch.Tensor
+    ns: torch.Tensor | None = None
+    n: int = 0
+    phase: int = 0
+    steps: int = 0
+
+
+def init_inplace(lat: Lattice, prm: N.lbm_params, rho0: float = 1.0, u0=None,
+                 ns: torch.Tensor | None = None, n: int | None = None,
+                 stream=None) -> InplaceState:
+    n = lat.base + lat.n_fluid if n is None else n
+    f = torch.empty((19, lat.stride), dtype=N.STORAGE_DTYPE[prm.storage], device=lat.device)
+    N._check("lbm_init", N.lbm_init(prm, n, lat.stride, f, rho0, u0, stream))
+    if ns is not None:
+        assert ns.dtype == torch.float64 and ns.numel() >= n and ns.is_contiguous()
+    return InplaceState(lat, prm, f, ns, n, 0, 0)
+
+
+def step_inplace(state: InplaceState, n_steps: int = 1, comp: Compressed | None = None,
+                 stream=None) -> InplaceState:
+    lat = state.lattice
+    codes = recs = None
+    if comp is not None:
+        assert comp.n == state.n and comp.codes.shape[1] == lat.stride
+        codes, recs = comp.codes, comp.tile_records
+    st = N.lbm_step_inplace(state.params, state.n, lat.stride, lat.adj, codes, recs, state.ns,
+                            state.f, state.phase, n_steps, stream)
+    N._check("lbm_step_inplace", st)
+    state.phase = (state.phase + n_steps) % 2
     state.steps += n_steps
     return state
 

@@ -42,13 +42,41 @@ def candidate_strides(n: int) -> list[int]:
     return sorted(c for c in cands if c >= n)
 
 
-def _time_sweeps(lat, prm, sweeps, stream):
-    st = L.init(lat, prm)
-    L.step(st, 2)
+SWEEPS = ("full", "c16", "inplace", "inplace_c16")
+
+
+class Sweeper:
+    """One way of stepping a lattice: the two-array sweep over the full
+    adjacency list ("full") or over 16-bit codes ("c16"), or the in-place
+    sweep on one array over either ("inplace", "inplace_c16").  Results are
+    bitwise the same after an even number of steps."""
+
+    def __init__(self, lat, kind: str = "full"):
+        assert kind in SWEEPS, kind
+        self.lat, self.kind = lat, kind
+        self.comp = L.compress(lat) if kind.endswith("c16") else None
+
+    def init(self, prm, **kw):
+        if self.kind.startswith("inplace"):
+            return L.init_inplace(self.lat, prm, **kw)
+        return L.init(self.lat, prm, **kw)
+
+    def step(self, st, n_steps: int):
+        if self.kind == "full":
+            return L.step(st, n_steps)
+        if self.kind == "c16":
+            return L.step_c16(st, self.comp, n_steps)
+        return L.step_inplace(st, n_steps, self.comp)
+
+
+def _time_sweeps(lat, prm, sweeps, stream, sweeper=None):
+    sw = sweeper or Sweeper(lat)
+    st = sw.init(prm)
+    sw.step(st, 2)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    L.step(st, sweeps)
+    sw.step(st, sweeps)
     e1.record(stream)
     e1.synchronize()
     return e0.elapsed_time(e1) / 1e3 / sweeps
@@ -57,8 +85,12 @@ def _time_sweeps(lat, prm, sweeps, stream):
 def tune_layout(flags: torch.Tensor, periodic: int, order: str = "lex", param: int = 0,
                 storage: str = "f64", force=(1e-6, 0.0, 0.0), sweeps: int = 6,
                 candidates: list[int] | None = None,
-                chunks: tuple = (1, 4, 16, 64, 0), finalists: int = 4) -> Layout:
+                chunks: tuple = (1, 4, 16, 64, 0), finalists: int = 4,
+                sweep: str = "full") -> Layout:
     """Time the candidate layouts on this geometry and return the fastest.
+
+    `sweep` names the sweep being tuned (see Sweeper); timed runs use an even
+    number of sweeps.
 
     Two stages: every candidate is timed over `sweeps` sweeps; the best
     `finalists` are timed again, twice each and interleaved, over 3 x
@@ -66,26 +98,27 @@ def tune_layout(flags: torch.Tensor, periodic: int, order: str = "lex", param: i
     enough to mis-rank layouts a few percent apart)."""
     n = L.count_fluid(flags, periodic, order, param)
     cands = candidates or candidate_strides(n)
+    sweeps += sweeps % 2
     table = []
     stream = torch.cuda.current_stream()
     lats = {}
     for S in cands:
-        lat = L.build(flags, periodic, order, param, stride=S)
+        sw = Sweeper(L.build(flags, periodic, order, param, stride=S), sweep)
         for nt in (False, True):
             for chunk in chunks:
                 prm = L.params(0.8, 3.0 / 16.0, force, storage, nontemporal=nt, xcd_chunk=chunk)
-                t = _time_sweeps(lat, prm, sweeps, stream)
+                t = _time_sweeps(sw.lat, prm, sweeps, stream, sw)
                 table.append((S, nt, chunk, round(n / t / 1e6, 1)))
-        del lat
+        del sw
     top = sorted(table, key=lambda r: -r[3])[:max(1, finalists)]
     totals = {}
     for _ in range(2):
         for S, nt, chunk, _r in top:
             if S not in lats:
                 lats.clear()
-                lats[S] = L.build(flags, periodic, order, param, stride=S)
+                lats[S] = Sweeper(L.build(flags, periodic, order, param, stride=S), sweep)
             prm = L.params(0.8, 3.0 / 16.0, force, storage, nontemporal=nt, xcd_chunk=chunk)
-            t = _time_sweeps(lats[S], prm, 3 * sweeps, stream)
+            t = _time_sweeps(lats[S].lat, prm, 3 * sweeps, stream, lats[S])
             totals[(S, nt, chunk)] = totals.get((S, nt, chunk), 0.0) + t
     (S, nt, chunk), tsum = min(totals.items(), key=lambda kv: kv[1])
     best = Layout(S, nt, chunk, n / (tsum / 2) / 1e6)
@@ -108,7 +141,7 @@ def crop_sample(flags: torch.Tensor, fraction: float) -> torch.Tensor:
 
 def tune_ordering(flags: torch.Tensor, periodic: int, storage: str = "f64",
                   candidates=ORDER_CANDIDATES, sample: float | None = None,
-                  force=(1e-6, 0.0, 0.0), sweeps: int = 4):
+                  force=(1e-6, 0.0, 0.0), sweeps: int = 4, sweep: str = "full"):
     """Pick the cell ordering (and layout) with the highest sweep rate.
 
     The paper proposes choosing the blocking factor by simulating samples of
@@ -126,13 +159,14 @@ def tune_ordering(flags: torch.Tensor, periodic: int, storage: str = "f64",
             continue
         lay = tune_layout(probe, periodic, order, param, storage, force, sweeps=sweeps,
                           candidates=sorted({L.aligned_stride(n), candidate_strides(n)[-3]}),
-                          chunks=(1, 0))
+                          chunks=(1, 0), sweep=sweep)
         table.append((order, param, round(lay.mflups, 1)))
         if best is None or lay.mflups > best[2].mflups:
             best = (order, param, lay)
     order, param, lay = best
     if sample:  # re-tune the layout of the chosen ordering on the full geometry
-        lay = tune_layout(flags, periodic, order, param, storage, force, sweeps=sweeps)
+        lay = tune_layout(flags, periodic, order, param, storage, force, sweeps=sweeps,
+                          sweep=sweep)
     return order, param, lay, table
 
 

@@ -159,3 +159,28 @@ def test_compressed_adjacency_argument_errors(lib):
     assert step(steps=-1) == N.LBM_EINVAL
     assert step(stride=(1 << 32) // 19 + 1) == N.LBM_EOVERFLOW
     assert step(steps=0) == N.LBM_OK                  # nothing to do, nothing launched
+
+
+def test_inplace_argument_errors(lib):
+    from paper_1111_1129_amd import _native as N
+    P = C.c_void_p
+    lib.lbm_step_inplace.restype = C.c_int32
+    lib.lbm_step_inplace.argtypes = [C.POINTER(N.lbm_params), C.c_int64, C.c_int64, P, P, P, P,
+                                     P, C.c_int32, C.c_int32, P]
+    good = N.make_params(0.8, 3 / 16, (1e-6, 0, 0), "f64")
+    d = P(4096)
+
+    def step(p=good, n=10, stride=10, adj=d, codes=None, recs=None, f=d, phase=0, steps=1):
+        return lib.lbm_step_inplace(C.byref(p), n, stride, adj, codes, recs, None, f, phase,
+                                    steps, None)
+
+    assert step(p=N.make_params(0.8, 0.0)) == N.LBM_EINVAL
+    assert step(adj=None) == N.LBM_EINVAL
+    assert step(f=None) == N.LBM_EINVAL
+    assert step(phase=2) == N.LBM_EINVAL
+    assert step(codes=d) == N.LBM_EINVAL          # codes without their tile records
+    assert step(recs=d) == N.LBM_EINVAL
+    assert step(stride=9) == N.LBM_EINVAL
+    assert step(steps=-2) == N.LBM_EINVAL
+    assert step(stride=(1 << 32) // 19 + 1) == N.LBM_EOVERFLOW
+    assert step(steps=0) == N.LBM_OK
