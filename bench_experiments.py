@@ -434,3 +434,64 @@ def compressed(a):
             emit(rec)
             del lat, comp, res
             torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------------------
+def oracle_rates(a):
+    """The plain FP64 oracle on the host cores, one thread and all threads:
+    sweep rate on the small packing and on the tube for each ordering, and the
+    forward and adjoint step rates on the PBB box (the CPU side of every GPU
+    number; no GPU work)."""
+    import oracle as O
+    all_threads = O.max_threads()
+    prm = O.TRT(0.8, 3 / 16, (1e-6, 0.0, 0.0))
+    cases = [("small_packing", I.packing_small(1), [("lex", 0)], 50),
+             ("tube_packing", I.packing_tube(2),
+              [("lex", 0), ("blocked", 16), ("morton1", 0), ("morton2", 0), ("random", 22)], 2)]
+    for name, g, orders, steps in cases:
+        for order, param in orders:
+            sp = O.build(g.flags, g.periodic, order, param)
+            n = sp.n_fluid
+            rec = {"experiment": "oracle_rates", "workload": name, "order": order, "param": param,
+                   "n_fluid": n, "steps": steps}
+            for threads in (1, all_threads):
+                O.set_threads(threads)
+                f = O.init(n)
+                h = np.empty_like(f)
+                O.step(prm, sp.adj, f, h)
+                t0 = time.perf_counter()
+                for _ in range(steps):
+                    O.step(prm, sp.adj, f, h)
+                    f, h = h, f
+                dt = time.perf_counter() - t0
+                rec[f"mflups_{threads}_threads"] = round(n * steps / dt / 1e6, 2)
+            emit(rec)
+            del sp
+    g = I.pbb_box(4)
+    sp = O.build(g.flags, g.periodic, "lex")
+    n = sp.n_fluid
+    ns_list = np.ascontiguousarray(g.ns.reshape(-1)[sp.cell_of[:n].astype(np.int64)],
+                                   dtype=np.float64)
+    f = O.init(n, shifted=True)
+    h = np.empty_like(f)
+    lam = np.zeros_like(f)
+    lam2 = np.zeros_like(f)
+    grad = np.zeros(n)
+    rec = {"experiment": "oracle_rates", "workload": "pbb_box 128^3", "n_fluid": n, "steps": 3}
+    for threads in (1, all_threads):
+        O.set_threads(threads)
+        t0 = time.perf_counter()
+        for _ in range(3):
+            O.step(prm, sp.adj, f, h, ns=ns_list)
+            f, h = h, f
+        t_fwd = time.perf_counter() - t0
+        O.adjoint_step(prm, sp.adj, f, ns_list, None, lam, grad)
+        t0 = time.perf_counter()
+        for _ in range(3):
+            O.adjoint_step(prm, sp.adj, f, ns_list, lam, lam2, grad)
+            lam, lam2 = lam2, lam
+        t_adj = time.perf_counter() - t0
+        rec[f"forward_mcells_per_s_{threads}_threads"] = round(n * 3 / t_fwd / 1e6, 2)
+        rec[f"adjoint_mcells_per_s_{threads}_threads"] = round(n * 3 / t_adj / 1e6, 2)
+    O.set_threads(all_threads)
+    emit(rec)
