@@ -246,6 +246,15 @@ def batched(a):
         stp = batch.init(prm)
         t_pers, _ = timed(lambda: L.step(stp, steps, persistent=True, segments=batch.segments))
         same = bool(torch.equal(stp.f[:, :tot_n], f_step))
+        # the same concatenated list swept over 16-bit adjacency codes (tiles
+        # that straddle two geometries escape to the full list)
+        comp = L.compress(batch.lattice, n=tot_n)
+        stc = batch.init(prm)
+        L.step_c16(stc, comp, 2)
+        stc = batch.init(prm)
+        t_c16, _ = timed(lambda: L.step_c16(stc, comp, steps))
+        same_c16 = bool(torch.equal(stc.f[:, :tot_n], f_step))
+        del stc
         solos = []
         for fl, g in zip(flags, geoms):
             lat = L.build(fl, g.periodic, "lex")
@@ -281,6 +290,8 @@ def batched(a):
               "mflups_persistent": round(tot_n * steps / t_pers / 1e6, 1),
               "mflups_launch_per_step": round(tot_n * steps / t_step / 1e6, 1),
               "mflups_separate_launches": round(tot_n * steps / t_sep / 1e6, 1),
+              "mflups_c16_per_step": round(tot_n * steps / t_c16 / 1e6, 1),
+              "c16_escapes": comp.n_escapes, "c16_equals_per_step": same_c16,
               "persistent_equals_per_step": same,
               "gbs_persistent": round(BYTES[storage] * tot_n * steps / t_pers / 1e9, 1),
               "gbs_launch_per_step": round(BYTES[storage] * tot_n * steps / t_step / 1e9, 1),
