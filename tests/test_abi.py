@@ -184,3 +184,51 @@ def test_inplace_argument_errors(lib):
     assert step(steps=-2) == N.LBM_EINVAL
     assert step(stride=(1 << 32) // 19 + 1) == N.LBM_EOVERFLOW
     assert step(steps=0) == N.LBM_OK
+
+
+C_CLIENT = r"""
+#include <stdio.h>
+#include <string.h>
+#include "lbm.h"
+
+int main(void) {
+    size_t ws = 0;
+    int64_t esc = 0;
+    lbm_params p;
+    memset(&p, 0, sizeof p);
+    p.tau_plus = 0.8;
+    p.magic = 3.0 / 16.0;
+    p.storage = LBM_F64;
+    if (lbm_version() < 10000) return 1;
+    if (strcmp(lbm_status_string(LBM_OK), "unknown status") == 0) return 2;
+    if (lbm_compress_adjacency(10, 10, NULL, NULL, NULL, &esc, NULL, &ws, NULL) != LBM_OK) return 3;
+    if (ws != 256) return 4;
+    p.tau_plus = 0.5; /* tau+ = 1/2 is rejected on the host */
+    if (lbm_step_inplace(&p, 10, 10, (const uint32_t*)0x1000, NULL, NULL, NULL, (void*)0x2000, 0, 1,
+                         NULL) != LBM_EINVAL) return 5;
+    printf("c client ok %d\n", lbm_version());
+    return 0;
+}
+"""
+
+
+def test_c_client_compiles_links_and_runs(tmp_path):
+    """The header is plain C and the library's host-side entry points work
+    from a C program (no GPU call is made)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "client.c"
+    src.write_text(C_CLIENT)
+    exe = tmp_path / "client"
+    libdir = os.path.dirname(LIB)
+    res = subprocess.run([cc, "-std=c99", "-Wall", "-Werror", f"-I{os.path.dirname(HEADER)}",
+                          str(src), "-o", str(exe), f"-L{libdir}", "-llbm",
+                          f"-Wl,-rpath,{libdir}", "-Wl,-rpath,/opt/rocm/lib"],
+                         capture_output=True, text=True)
+    assert res.returncode == 0, res.stderr
+    run = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert run.returncode == 0, (run.returncode, run.stdout, run.stderr)
+    assert "c client ok" in run.stdout
