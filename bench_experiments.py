@@ -134,13 +134,35 @@ def adjoint(a):
     n_edge = 128 // a.scale
     g = I.pbb_box(4, n=n_edge)
     flags = dev_flags(g)
-    lat = L.build(flags, g.periodic, "lex")
+    # layout of the adjoint kernel: row stride x store policy x XCD mapping,
+    # each timed over 20 adjoint steps; the fastest is used for the run
+    n = L.count_fluid(flags, g.periodic, "lex")
+    table = []
+    for S in sorted({L.aligned_stride(n), candidate_strides(n)[-2]}):
+        lat = L.build(flags, g.periodic, "lex", stride=S)
+        nsl = torch.zeros(S, dtype=torch.float64, device="cuda")
+        nsl[:n] = 0.5
+        for nt in (False, True):
+            for chunk in (1, 4, 16, 0):
+                prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), "f64s", nontemporal=nt, xcd_chunk=chunk)
+                st = L.init(lat, prm, ns=nsl)
+                lam = torch.zeros((19, S), dtype=torch.float64, device="cuda")
+                lam2 = torch.empty_like(lam)
+                gr = torch.zeros(S, dtype=torch.float64, device="cuda")
+                N.lbm_step_adjoint(prm, n, S, lat.adj, st.f, nsl, lam, lam2, gr)
+                t, _ = timed(lambda: [N.lbm_step_adjoint(prm, n, S, lat.adj, st.f, nsl, lam, lam2, gr)
+                                      for _ in range(20)])
+                table.append((S, nt, chunk, round(t / 20 * 1e6, 1)))
+                del st, lam, lam2, gr
+        del lat
+    S_best, nt_best, chunk_best, _ = min(table, key=lambda r: r[3])
+    lat = L.build(flags, g.periodic, "lex", stride=S_best)
     n, S = lat.n_fluid, lat.stride
     cell = lat.cell_of.cpu().numpy()
     ns_host = np.zeros(S)
     ns_host[:n] = g.ns.ravel()[cell]
     ns = torch.from_numpy(ns_host).cuda()
-    prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), "f64s")
+    prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), "f64s", nontemporal=nt_best, xcd_chunk=chunk_best)
     T, k = 500, 22
     t_fwd, (J, ckpts, _) = timed(lambda: AD.forward_states(lat, prm, ns, T, k))
     t_bwd, grad = timed(lambda: AD.adjoint_gradient(lat, prm, ns, T, k, ckpts))
@@ -211,6 +233,7 @@ def adjoint(a):
     emit({"experiment": "adjoint", "workload": f"pbb_box {n_edge}^3", "n_fluid": n, "steps": T,
           "checkpoint_every": k, "J_mean_ux": float(J), "forward_s": round(t_fwd, 4),
           "backward_s": round(t_bwd, 4), "backward_over_forward": round(t_bwd / t_fwd, 2),
+          "layout": [S, nt_best, chunk_best], "layout_table_us": table,
           "adjoint_step_us": round(t_adj * 1e6, 1),
           "adjoint_gbs": round(552 * n / t_adj / 1e9, 1),
           "adjoint_hbm_frac": round(552 * n / t_adj / 1e9 / PEAK, 4),

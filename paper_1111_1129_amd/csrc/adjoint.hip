@@ -23,15 +23,16 @@ namespace lbm {
 
 constexpr int kAdjBlock = 256;
 
-template <bool PBB>
+template <bool PBB, bool NT>
 __global__ __launch_bounds__(kAdjBlock) void k_adjoint(const double* __restrict__ f_t,
                                                        const uint32_t* __restrict__ adj,
                                                        const double* __restrict__ ns,
                                                        const double* __restrict__ lam_next,
                                                        double* __restrict__ lam_t,
                                                        double* __restrict__ grad, int64_t n,
-                                                       int64_t stride, TrtConst c) {
-    const int64_t m = int64_t(blockIdx.x) * kAdjBlock + threadIdx.x;
+                                                       int64_t stride, TrtConst c,
+                                                       int chunk_shift) {
+    const int64_t m = logical_block(chunk_shift) * kAdjBlock + threadIdx.x;
     if (m >= n) return;
     uint32_t A[Q];
     A[0] = uint32_t(m);
@@ -74,7 +75,7 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(const double* __restrict_
     const double P = sp * m0;
     double nu0 = mu[0] - sp * mu[0] + P;
     if constexpr (PBB) nu0 = (1.0 - s) * nu0 + s * mu[0];
-    lam_t[A[0]] = nu0;
+    st<double, double, NT>(lam_t + A[0], nu0);
 #pragma unroll
     for (int k = 0; k < NPAIR; ++k) {
         const int a = 2 * k + 1, b = 2 * k + 2;
@@ -89,8 +90,8 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(const double* __restrict_
             na = (1.0 - s) * na + s * mu[b];
             nb = (1.0 - s) * nb + s * mu[a];
         }
-        lam_t[A[a]] = na;
-        lam_t[A[b]] = nb;
+        st<double, double, NT>(lam_t + A[a], na);
+        st<double, double, NT>(lam_t + A[b], nb);
     }
 }
 
@@ -126,9 +127,16 @@ extern "C" lbm_status lbm_step_adjoint(const lbm_params* p, int64_t n, int64_t s
     if (!f_t) return LBM_EINVAL;
     const TrtConst c = make_trt_const(*p);
     const double* f = static_cast<const double*>(f_t);
-    if (ns)
-        k_adjoint<true><<<grid, kAdjBlock, 0, s>>>(f, adj, ns, lam_next, lam_t, grad_ns, n, stride, c);
-    else
-        k_adjoint<false><<<grid, kAdjBlock, 0, s>>>(f, adj, ns, lam_next, lam_t, nullptr, n, stride, c);
+    // the sweep's launch options: workgroup-to-XCD mapping, nontemporal stores
+    const int cs = chunk_shift_for(p->flags, n, kAdjBlock);
+    const dim3 g{unsigned(grid_blocks(n, kAdjBlock, cs))}, b{unsigned(kAdjBlock)};
+    const bool nt = p->flags & LBM_FLAG_NONTEMPORAL;
+    if (ns) {
+        if (nt) k_adjoint<true, true><<<g, b, 0, s>>>(f, adj, ns, lam_next, lam_t, grad_ns, n, stride, c, cs);
+        else k_adjoint<true, false><<<g, b, 0, s>>>(f, adj, ns, lam_next, lam_t, grad_ns, n, stride, c, cs);
+    } else {
+        if (nt) k_adjoint<false, true><<<g, b, 0, s>>>(f, adj, ns, lam_next, lam_t, nullptr, n, stride, c, cs);
+        else k_adjoint<false, false><<<g, b, 0, s>>>(f, adj, ns, lam_next, lam_t, nullptr, n, stride, c, cs);
+    }
     return after_launch();
 }

@@ -27,54 +27,73 @@ namespace lbm {
 constexpr int kCTile = kCodeTile;  // cells per tile = workgroup size of the sweep
 constexpr int kRec = kCodeRec;
 
+// One workgroup per tile.  Every thread stores its 18 offsets (int32: an
+// offset is below stride < 2^32 / 19 in magnitude) to LDS; after one barrier
+// each wave reduces the smallest and largest offset of every fourth
+// direction (4 values per lane, then shuffles), and after a second barrier
+// every thread encodes its entries against the 18 bases.
 __global__ __launch_bounds__(kCTile) void k_compress(const uint32_t* __restrict__ adj, int64_t n,
                                                      int64_t stride, int16_t* __restrict__ codes,
                                                      int32_t* __restrict__ rec,
                                                      unsigned long long* __restrict__ escapes) {
-    __shared__ int64_t lo[kCTile], hi[kCTile];
+    constexpr int kWaves = kCTile / 64;
+    __shared__ int32_t lo_s[Q - 1][kCTile], hi_s[Q - 1][kCTile];
+    __shared__ int32_t base_s[Q - 1];
     __shared__ unsigned int tile_esc;
     const int64_t tile = blockIdx.x;
     const int64_t m = tile * kCTile + threadIdx.x;
     const bool live = m < n;
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     if (threadIdx.x == 0) tile_esc = 0;
-    unsigned int esc = 0;
+    int32_t d[Q - 1];
+    uint32_t streams = 0;  // bit k: entry k streams (is not a bounce-back)
+#pragma unroll
     for (int k = 0; k < Q - 1; ++k) {
         const int64_t i = k + 1;
-        int64_t d = 0;
-        bool streams = false;
+        d[k] = 0;
         if (live) {
             const int64_t slot = adj[k * stride + m];
-            streams = slot / stride == i;
-            d = slot - i * stride - m;
+            // streaming entries lie in row i (a range test: no 64-bit division)
+            if (slot >= i * stride && slot < (i + 1) * stride) streams |= 1u << k;
+            d[k] = int32_t(slot - i * stride - m);
         }
-        lo[threadIdx.x] = streams ? d : INT64_MAX;
-        hi[threadIdx.x] = streams ? d : INT64_MIN;
-        __syncthreads();
-        for (int off = kCTile / 2; off > 0; off >>= 1) {
-            if (threadIdx.x < off) {
-                lo[threadIdx.x] = min(lo[threadIdx.x], lo[threadIdx.x + off]);
-                hi[threadIdx.x] = max(hi[threadIdx.x], hi[threadIdx.x + off]);
-            }
-            __syncthreads();
+        const bool st_k = (streams >> k) & 1u;
+        lo_s[k][threadIdx.x] = st_k ? d[k] : INT32_MAX;
+        hi_s[k][threadIdx.x] = st_k ? d[k] : INT32_MIN;
+    }
+    __syncthreads();
+    for (int k = wave; k < Q - 1; k += kWaves) {
+        int32_t lo = lo_s[k][lane], hi = hi_s[k][lane];
+        for (int j = 1; j < kWaves; ++j) {
+            lo = min(lo, lo_s[k][lane + 64 * j]);
+            hi = max(hi, hi_s[k][lane + 64 * j]);
         }
-        const int64_t mn = lo[0], mx = hi[0];
-        // midpoint of the tile's range (0 if nothing streams); fits int32
-        // because |src - m| < 2^32 / 19
-        const int64_t base = (mn <= mx) ? mn + (mx - mn) / 2 : 0;
-        if (threadIdx.x == 0) rec[tile * kRec + k] = int32_t(base);
+        for (int off = 32; off > 0; off >>= 1) {
+            lo = min(lo, __shfl_xor(lo, off));
+            hi = max(hi, __shfl_xor(hi, off));
+        }
+        // midpoint of the tile's range (0 if nothing streams)
+        if (lane == 0) base_s[k] = (lo <= hi) ? int32_t(lo + (int64_t(hi) - lo) / 2) : 0;
+    }
+    __syncthreads();
+    unsigned int esc = 0;
+#pragma unroll
+    for (int k = 0; k < Q - 1; ++k) {
+        const int32_t base = base_s[k];
+        if (threadIdx.x == 0) rec[tile * kRec + k] = base;
         if (live) {
+            const int64_t r = int64_t(d[k]) - base;
             int16_t c;
-            if (!streams) {
+            if (!((streams >> k) & 1u)) {
                 c = kCodeBounce;
-            } else if (d - base >= kCodeMin && d - base <= kCodeMax) {
-                c = int16_t(d - base);
+            } else if (r >= kCodeMin && r <= kCodeMax) {
+                c = int16_t(r);
             } else {
                 c = kCodeEscape;
                 ++esc;
             }
             codes[k * stride + m] = c;
         }
-        __syncthreads();  // lo/hi are reused by the next direction
     }
     if (esc) atomicAdd(&tile_esc, esc);
     __syncthreads();

@@ -41,10 +41,9 @@ __global__ __launch_bounds__(kPartBlock) void k_partition_links(
 #pragma unroll
     for (int k = 0; k < Q - 1; ++k) {
         const int64_t slot = adj[k * stride + m];
-        const int64_t dir = slot / stride;
-        if (dir != k + 1) continue;  // bounce-back: the cell's own population
-        const int64_t src = slot - dir * stride;
-        if (src < 0 || src >= n) continue;  // not a listed cell of [0, n)
+        const int64_t src = slot - (k + 1) * stride;
+        if (src < 0 || src >= stride) continue;  // bounce-back (another row): own population
+        if (src >= n) continue;  // not a listed cell of [0, n)
         const int64_t b = chunk_of(src, n, G);
         if (b == a) continue;
         ++links;
