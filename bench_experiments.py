@@ -81,6 +81,20 @@ def precision(a):
                    "hbm_frac": round(BYTES[st] * n * sweeps / t / 1e9 / PEAK, 4),
                    "stride": lat.stride, "nt": lay.nontemporal, "chunk": lay.xcd_chunk,
                    "mass": float(tot[0, 0]), "mean_ux": float(tot[0, 1]) / n}
+            if gx == 1e-6:
+                # the same sweep over 16-bit adjacency codes (bitwise the same state)
+                comp = L.compress(lat)
+                sc = L.init(lat, prm)
+                L.step_c16(sc, comp, 2)
+                sc = L.init(lat, prm)
+                tc, _ = timed(lambda: L.step_c16(sc, comp, sweeps))
+                rec["mflups_c16"] = round(n * sweeps / tc / 1e6, 1)
+                rec["c16_equal"] = bool(torch.equal(sc.f[:, :n], state.f[:, :n]))
+                if st == "f64":
+                    t_ref_c16 = tc
+                else:
+                    rec["speedup_c16_vs_f64_c16"] = round(t_ref_c16 / tc, 3)
+                del sc, comp
             if st == "f64":
                 ref, t_ref = u.clone(), t
             else:
