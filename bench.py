@@ -168,7 +168,7 @@ def cpu_baseline(geom, order, param, storage, target_s, n_ref):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     import torch
     from paper_1111_1129_amd import _native as N
