@@ -61,6 +61,28 @@ def test_adjoint_step_vs_oracle(pbb):
     np.testing.assert_array_equal(seed.cpu().numpy()[:, :n], o_seed[:, :n])
 
 
+def test_adjoint_launch_options_are_bitwise_identical():
+    """Store policy and workgroup-to-XCD mapping change only the speed."""
+    g = I.pbb_box(4, n=40)
+    print_case("adjoint", "launch options", "pbb_box 40^3")
+    lat = L.build(dev_flags(g), g.periodic, "lex")
+    n, S = lat.n_fluid, lat.stride
+    ns = torch.zeros(S, dtype=torch.float64, device="cuda")
+    ns[:n] = torch.from_numpy(g.ns.ravel()[lat.cell_of.cpu().numpy()]).cuda()
+    f = torch.from_numpy(random_state(n, 3, amp=1e-3, shifted=True, stride=S)).cuda()
+    lam = torch.zeros((19, S), dtype=torch.float64, device="cuda")
+    lam[:, :n] = torch.randn((19, n), dtype=torch.float64, generator=torch.Generator().manual_seed(5)).cuda()
+    outs = []
+    for nt, chunk in ((False, 0), (True, 1), (False, 4), (True, 0)):
+        prm = L.params(0.8, 3 / 16, (1e-5, 0, 0), "f64s", nontemporal=nt, xcd_chunk=chunk)
+        lt = torch.zeros((19, S), dtype=torch.float64, device="cuda")
+        gr = torch.zeros(S, dtype=torch.float64, device="cuda")
+        assert N.lbm_step_adjoint(prm, n, S, lat.adj, f, ns, lam, lt, gr) == 0
+        outs.append((lt[:, :n].clone(), gr[:n].clone()))
+    for lt, gr in outs[1:]:
+        assert torch.equal(lt, outs[0][0]) and torch.equal(gr, outs[0][1])
+
+
 def test_gradient_vs_oracle_with_checkpoints(pbb):
     g, sp, lat, ns = pbb
     prm = L.params(0.8, 3 / 16, (1e-5, 0, 0), "f64s")
