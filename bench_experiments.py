@@ -370,7 +370,9 @@ def orderings(a):
               "hbm_frac": round(376 * n * sweeps / t / 1e9 / PEAK, 4),
               "stride": lay.stride, "nt": lay.nontemporal, "chunk": lay.xcd_chunk,
               "assembly_ms": round(t_asm * 1e3, 2),
-              "assembly_mcells_per_s": round(flags.numel() / t_asm / 1e6, 1)})
+              "assembly_mcells_per_s": round(flags.numel() / t_asm / 1e6, 1),
+              # flag read + index_of write per box cell, cell_of + adjacency per fluid cell
+              "assembly_gbs": round((5 * flags.numel() + 76 * n) / t_asm / 1e9, 1)})
         del lat, st
         torch.cuda.empty_cache()
 
@@ -543,3 +545,43 @@ def oracle_rates(a):
         rec[f"adjoint_mcells_per_s_{threads}_threads"] = round(n * 3 / t_adj / 1e6, 2)
     O.set_threads(all_threads)
     emit(rec)
+
+
+# ---------------------------------------------------------------------------
+def pbb(a):
+    """The sweep with partial bounce-back (one more FP64 value per cell: the
+    solid fraction) on the tube with a uniform random field and on the PBB box
+    with its smoothed field: full list and 16-bit codes."""
+    cases = [("tube_packing", I.packing_tube(2), None), ("pbb_box 128^3", I.pbb_box(4), "field")]
+    sweeps = 400
+    for name, g, kind in cases:
+        flags = dev_flags(g)
+        for storage in ("f64", "f64s"):
+            lay = tune_layout(flags, g.periodic, "lex", 0, storage, sweeps=4)
+            lat = L.build(flags, g.periodic, "lex", stride=lay.stride)
+            n, S = lat.n_fluid, lat.stride
+            ns = torch.zeros(S, dtype=torch.float64, device="cuda")
+            if kind == "field":
+                ns[:n] = torch.from_numpy(g.ns.ravel()[lat.cell_of.cpu().numpy()]).cuda()
+            else:
+                ns[:n] = torch.rand(n, dtype=torch.float64,
+                                    generator=torch.Generator().manual_seed(7)).cuda()
+            prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), storage, nontemporal=lay.nontemporal,
+                           xcd_chunk=lay.xcd_chunk)
+            comp = L.compress(lat)
+            res = {}
+            for sweep in ("full", "c16"):
+                st = L.init(lat, prm, ns=ns)
+                run = (lambda k: L.step(st, k)) if sweep == "full" else \
+                    (lambda k: L.step_c16(st, comp, k))
+                run(2)
+                t, _ = timed(lambda: run(sweeps))
+                byt = 384.0 if sweep == "full" else 348 + 80 / 256
+                res[sweep] = {"mflups": round(n * sweeps / t / 1e6, 1),
+                              "bytes_per_update": round(byt, 2),
+                              "hbm_frac": round(byt * n * sweeps / t / 1e9 / PEAK, 4)}
+                del st
+            emit({"experiment": "pbb", "workload": name, "n_fluid": n, "storage": storage,
+                  "sweeps": sweeps, "layout": [lay.stride, lay.nontemporal, lay.xcd_chunk], **res})
+            del lat, comp, ns
+            torch.cuda.empty_cache()
