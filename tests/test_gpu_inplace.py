@@ -119,3 +119,26 @@ def test_full_size_tube():
     assert torch.equal(st.f[:, :lat.n_fluid], ref)
     _, _, tot = L.moments(st, fields=False)
     assert abs(float(tot[0, 0]) / lat.n_fluid - 1.0) < 1e-12  # mass is conserved
+
+
+def test_sweeper_kinds_and_tuner():
+    """Every sweep kind the tuner and the benchmark use ends in the same state;
+    the tuner returns an aligned stride and a valid store/XCD choice."""
+    from paper_1111_1129_amd.tune import SWEEPS, Sweeper, tune_layout
+    g = I.packing_small(1)
+    flags = dev_flags(g)
+    print_case("inplace", "sweeper kinds + tuner")
+    lat = L.build(flags, g.periodic, "lex", 0)
+    prm = L.params(0.8, 3 / 16, (1e-5, 0, 0), "f32s")
+    finals = []
+    for kind in SWEEPS:
+        sw = Sweeper(lat, kind)
+        st = sw.init(prm)
+        sw.step(st, 6)
+        finals.append(st.f[:, :lat.n_fluid].clone())
+    for f in finals[1:]:
+        assert torch.equal(f, finals[0])
+    lay = tune_layout(flags, g.periodic, "lex", 0, "f32s", sweeps=2, chunks=(1, 0), finalists=2,
+                      sweep="c16")
+    assert lay.stride >= lat.n_fluid and lay.stride % 64 == 0
+    assert lay.xcd_chunk in (1, 0) and lay.mflups > 0
