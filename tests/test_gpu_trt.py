@@ -224,30 +224,73 @@ def test_reduced_precision_one_step(small, storage):
     assert np.abs(gpu - f0.astype(np.float64)).max() > 10 * tol.max()
 
 
+def sampled_step_vs_oracle(lat, prm, st, advance, ranges):
+    """One more GPU step (`advance`) compared on sampled cell ranges with the
+    oracle's collision of the same gathered inputs.  The inputs are gathered
+    on the device through the adjacency (indexing only); the oracle then steps
+    them through an identity adjacency."""
+    S = lat.stride
+    idx = torch.cat([torch.arange(a, b, device="cuda") for a, b in ranges])
+    k = idx.numel()
+    slots = lat.adj[:, idx].to(torch.int64) & 0xFFFFFFFF
+    flat = st.f.reshape(-1)
+    gath = torch.empty((19, k), dtype=torch.float64, device="cuda")
+    gath[0] = st.f[0, idx]
+    gath[1:] = flat[slots]
+    gath = gath.cpu().numpy()
+    advance()
+    got = st.f[:, idx].cpu().numpy()
+    ident = ((np.arange(1, 19, dtype=np.uint64)[:, None] * k + np.arange(k, dtype=np.uint64)[None, :])
+             .astype(np.uint32))
+    orc = np.zeros_like(gath)
+    O.step(oracle_params(prm), ident, np.ascontiguousarray(gath), orc)
+    assert S >= lat.n_fluid
+    return rel_err_f64(got, orc)
+
+
 def test_full_size_tube_sampled_step():
-    """The full 256^3 tube in the benchmark's launch configuration: after 20
-    GPU steps from a random state, one more GPU step is compared on sampled
-    cell ranges (head, middle, ragged tail) with the oracle's step of the same
-    input state."""
+    """The full 256^3 tube in the benchmark's launch configuration (sweep over
+    16-bit codes, row stride 2^23 + 1024, nontemporal stores, XCD chunk 1):
+    after 20 GPU steps from a random state, one more GPU step is compared on
+    sampled cell ranges (head, middle, ragged tail) with the oracle's step of
+    the same input state; the whole state conserves mass."""
     g = I.packing_tube(2)
-    lat = L.build(dev_flags(g), g.periodic, "lex")
+    lat = L.build(dev_flags(g), g.periodic, "lex", stride=8389632)
     n = lat.n_fluid
-    adj = lat.adj.cpu().numpy().view(np.uint32)
-    prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), "f64", nontemporal=True)
+    prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), "f64", nontemporal=True, xcd_chunk=1)
     print_case("tube full size", n)
+    comp = L.compress(lat)
     st = L.init(lat, prm)
     st.f.copy_(torch.from_numpy(random_state(n, 10, stride=lat.stride)))
-    L.step(st, 20)
-    f_t = st.f.cpu().numpy()
-    L.step(st, 1)
-    f_next = st.f.cpu().numpy()
-    orc = np.zeros_like(f_t)
+    L.step_c16(st, comp, 20)
+    mass0 = float(st.f[:, :n].sum())
     ranges = [(0, 4096), (n // 3, n // 3 + 3000), (n // 2 + 17, n // 2 + 5000), (n - 2049, n)]
-    for a, b in ranges:
-        O.step(oracle_params(prm), adj, f_t, orc, n0=a, n1=b)
-        assert rel_err_f64(f_next[:, a:b], orc[:, a:b]) <= TOL_F64
-    # and the whole state conserves mass
-    assert abs(f_next[:, :n].sum() - f_t[:, :n].sum()) <= 1e-12 * f_t[:, :n].sum()
+    err = sampled_step_vs_oracle(lat, prm, st, lambda: L.step_c16(st, comp, 1), ranges)
+    assert err <= TOL_F64
+    assert abs(float(st.f[:, :n].sum()) - mass0) <= 1e-12 * mass0
+
+
+def test_large_packing_full_size_sampled_step():
+    """The 512x512x1024 packing (107 M cells) at full size: 10 GPU steps over
+    16-bit codes from a random state, then one more step compared on sampled
+    ranges with the oracle."""
+    g = I.workload("large_packing")
+    lat = L.build(dev_flags(g), g.periodic, "lex")
+    n = lat.n_fluid
+    print_case("large packing full size", n)
+    prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), "f64", nontemporal=True, xcd_chunk=64)
+    comp = L.compress(lat)
+    st = L.init(lat, prm)
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    w = torch.from_numpy(W).cuda()[:, None]
+    st.f[:, :n] = w * (1.0 + 0.02 * torch.randn((19, n), dtype=torch.float64, device="cuda",
+                                                 generator=gen))
+    L.step_c16(st, comp, 10)
+    ranges = [(0, 4096), (n // 2, n // 2 + 4096), (n - 3001, n)]
+    err = sampled_step_vs_oracle(lat, prm, st, lambda: L.step_c16(st, comp, 1), ranges)
+    assert err <= TOL_F64
+    del st, comp, lat
+    torch.cuda.empty_cache()
 
 
 def test_large_packing_cropped_vs_oracle():
