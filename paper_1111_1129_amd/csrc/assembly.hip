@@ -256,6 +256,10 @@ struct AdjGeom {
     int64_t base, stride;
 };
 
+// One thread per fluid cell.  The 18 upstream box indices are computed
+// first without branches (a neighbour outside a non-periodic face reads the
+// cell's own entry and is then discarded), so the 18 index_of gathers are all
+// in flight at once instead of one round trip each.
 __global__ __launch_bounds__(256) void k_adjacency(const int32_t* __restrict__ cell_of,
                                                    const int32_t* __restrict__ index_of, int64_t nf,
                                                    AdjGeom g, uint32_t* __restrict__ adj) {
@@ -268,25 +272,33 @@ __global__ __launch_bounds__(256) void k_adjacency(const int32_t* __restrict__ c
     const int32_t y = int32_t(yz % ny);
     const int32_t z = int32_t(yz / ny);
     const int64_t self = g.base + m;
+    const int32_t dims[3] = {g.nx, g.ny, g.nz};
+    uint32_t at[Q - 1];
+    uint32_t outside = 0;  // bit k: the upstream cell of direction k + 1 is outside the box
 #pragma unroll
-    for (int i = 1; i < Q; ++i) {
+    for (int k = 0; k < Q - 1; ++k) {
+        const int i = k + 1;
         int32_t q[3] = {x - vel_x(i), y - vel_y(i), z - vel_z(i)};
-        const int32_t dims[3] = {g.nx, g.ny, g.nz};
-        bool inside = true;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            if (q[d] < 0 || q[d] >= dims[d]) {
-                if (g.periodic & (1u << d))
-                    q[d] = q[d] < 0 ? q[d] + dims[d] : q[d] - dims[d];
-                else
-                    inside = false;
-            }
+            const bool lo = q[d] < 0, hi = q[d] >= dims[d];
+            const bool wrap = (g.periodic >> d) & 1u;
+            if ((lo || hi) && !wrap) outside |= 1u << k;
+            q[d] = lo ? q[d] + dims[d] : (hi ? q[d] - dims[d] : q[d]);
         }
-        int32_t up = -1;
-        if (inside) up = index_of[int64_t(q[0]) + int64_t(g.nx) * (int64_t(q[1]) + int64_t(g.ny) * q[2])];
-        const uint64_t slot = up >= 0 ? uint64_t(i) * uint64_t(g.stride) + uint64_t(g.base) + uint64_t(up)
-                                      : uint64_t(opp(i)) * uint64_t(g.stride) + uint64_t(self);
-        adj[int64_t(i - 1) * g.stride + self] = uint32_t(slot);
+        const uint32_t ql = uint32_t(q[0]) + nx * (uint32_t(q[1]) + ny * uint32_t(q[2]));
+        at[k] = ((outside >> k) & 1u) ? lin : ql;
+    }
+    int32_t up[Q - 1];
+#pragma unroll
+    for (int k = 0; k < Q - 1; ++k) up[k] = index_of[at[k]];
+#pragma unroll
+    for (int k = 0; k < Q - 1; ++k) {
+        const int i = k + 1;
+        const bool stream = !((outside >> k) & 1u) && up[k] >= 0;
+        const uint64_t slot = stream ? uint64_t(i) * uint64_t(g.stride) + uint64_t(g.base) + uint64_t(up[k])
+                                     : uint64_t(opp(i)) * uint64_t(g.stride) + uint64_t(self);
+        adj[int64_t(k) * g.stride + self] = uint32_t(slot);
     }
 }
 
