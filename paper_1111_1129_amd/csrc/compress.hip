@@ -47,16 +47,19 @@ __global__ __launch_bounds__(kCTile) void k_compress(const uint32_t* __restrict_
     if (threadIdx.x == 0) tile_esc = 0;
     int32_t d[Q - 1];
     uint32_t streams = 0;  // bit k: entry k streams (is not a bounce-back)
+    // lanes past the list read cell 0 (n > 0) and are ignored: no branch
+    // around the loads, so all 18 are in flight at once
+    const int64_t mc = live ? m : 0;
+    uint32_t slot32[Q - 1];
+#pragma unroll
+    for (int k = 0; k < Q - 1; ++k) slot32[k] = adj[k * stride + mc];
 #pragma unroll
     for (int k = 0; k < Q - 1; ++k) {
         const int64_t i = k + 1;
-        d[k] = 0;
-        if (live) {
-            const int64_t slot = adj[k * stride + m];
-            // streaming entries lie in row i (a range test: no 64-bit division)
-            if (slot >= i * stride && slot < (i + 1) * stride) streams |= 1u << k;
-            d[k] = int32_t(slot - i * stride - m);
-        }
+        const int64_t slot = slot32[k];
+        // streaming entries lie in row i (a range test: no 64-bit division)
+        if (live && slot >= i * stride && slot < (i + 1) * stride) streams |= 1u << k;
+        d[k] = int32_t(slot - i * stride - mc);
         const bool st_k = (streams >> k) & 1u;
         lo_s[k][threadIdx.x] = st_k ? d[k] : INT32_MAX;
         hi_s[k][threadIdx.x] = st_k ? d[k] : INT32_MIN;

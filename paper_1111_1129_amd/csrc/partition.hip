@@ -38,9 +38,12 @@ __global__ __launch_bounds__(kPartBlock) void k_partition_links(
     if (m >= n) return;
     const int64_t a = chunk_of(m, n, G);
     unsigned int links = 0;
+    uint32_t slots[Q - 1];  // all 18 loads in flight before the first atomic
+#pragma unroll
+    for (int k = 0; k < Q - 1; ++k) slots[k] = adj[k * stride + m];
 #pragma unroll
     for (int k = 0; k < Q - 1; ++k) {
-        const int64_t slot = adj[k * stride + m];
+        const int64_t slot = slots[k];
         const int64_t src = slot - (k + 1) * stride;
         if (src < 0 || src >= stride) continue;  // bounce-back (another row): own population
         if (src >= n) continue;  // not a listed cell of [0, n)
