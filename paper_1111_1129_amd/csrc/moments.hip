@@ -57,10 +57,15 @@ __global__ __launch_bounds__(kMomBlock) void k_moments(const typename Storage<ST
     DD v[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
     if (local < cnt) {
         const int64_t m = n0 + local;
+        // the 18 adjacency rows first, then the 18 gathers: both batches in
+        // flight at once
+        uint32_t a[Q - 1];
+#pragma unroll
+        for (int k = 0; k < Q - 1; ++k) a[k] = adj[k * stride + m];
         double g[Q];
         g[0] = static_cast<double>(f[m]);
 #pragma unroll
-        for (int k = 0; k < Q - 1; ++k) g[k + 1] = static_cast<double>(f[adj[k * stride + m]]);
+        for (int k = 0; k < Q - 1; ++k) g[k + 1] = static_cast<double>(f[a[k]]);
         const CellMoments<double> cm = cell_moments(g);
         const double r = Storage<ST>::shifted ? 1.0 + cm.rho : cm.rho;
         const double ux = cm.jx + 0.5 * gx, uy = cm.jy + 0.5 * gy, uz = cm.jz + 0.5 * gz;
