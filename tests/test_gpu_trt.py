@@ -184,13 +184,14 @@ def test_moments_vs_oracle(small, storage):
 def test_moments_segments_and_determinism(small):
     g, sp, lat = small
     prm = L.params(0.8, 3 / 16, (1e-5, 0, 0), "f64")
-    st = run_gpu(lat, prm, random_state(sp.n_fluid, 8, stride=lat.stride), 3)
+    f = random_state(sp.n_fluid, 8, stride=lat.stride)
+    st = L.init(lat, prm)
+    st.f.copy_(torch.from_numpy(f))
     n = sp.n_fluid
     segs = [(0, 1000), (1000, 1), (1001, n - 1001)]
     _, _, t1 = L.moments(st, segments=segs)
     _, _, t2 = L.moments(st, segments=segs)
     assert torch.equal(t1, t2)
-    f = st.f.cpu().numpy()
     for k, (b, c) in enumerate(segs):
         _, _, ot = O.moments(oracle_params(prm), sp.adj, f, False, b, b + c)
         np.testing.assert_allclose(t1[k].cpu().numpy(), ot, rtol=1e-13, atol=1e-18)
@@ -224,72 +225,75 @@ def test_reduced_precision_one_step(small, storage):
     assert np.abs(gpu - f0.astype(np.float64)).max() > 10 * tol.max()
 
 
-def sampled_step_vs_oracle(lat, prm, st, advance, ranges):
-    """One more GPU step (`advance`) compared on sampled cell ranges with the
-    oracle's collision of the same gathered inputs.  The inputs are gathered
-    on the device through the adjacency (indexing only); the oracle then steps
-    them through an identity adjacency."""
+def sampled_step_vs_oracle(lat, sp, prm, st, advance, ranges, seed):
+    """One GPU step (`advance`) from a seeded state, compared on sampled cell
+    ranges with the oracle's step of the same state.
+
+    The state is the rest weights everywhere except the slots the sampled
+    cells read -- located through the oracle's own adjacency `sp` -- which get
+    seeded random values; both sides take their inputs from that one table,
+    and the oracle steps the sampled cells through an identity adjacency."""
     S = lat.stride
-    idx = torch.cat([torch.arange(a, b, device="cuda") for a, b in ranges])
-    k = idx.numel()
-    slots = lat.adj[:, idx].to(torch.int64) & 0xFFFFFFFF
-    flat = st.f.reshape(-1)
-    gath = torch.empty((19, k), dtype=torch.float64, device="cuda")
-    gath[0] = st.f[0, idx]
-    gath[1:] = flat[slots]
-    gath = gath.cpu().numpy()
+    cells = np.concatenate([np.arange(a, b) for a, b in ranges]).astype(np.int64)
+    k = cells.size
+    slots = np.empty((19, k), dtype=np.int64)
+    slots[0] = cells                                   # rest population: own slot of row 0
+    slots[1:] = sp.adj[:, cells].astype(np.int64)      # the oracle's pull adjacency
+    rows = slots // S
+    rng = np.random.default_rng(seed)
+    vals = W[rows] * (1.0 + 0.02 * rng.standard_normal(slots.shape))
+    w_dev = torch.from_numpy(W).cuda()
+    st.f.copy_(w_dev[:, None].expand(19, S))
+    st.f.view(-1)[torch.from_numpy(slots.ravel()).cuda()] = torch.from_numpy(vals.ravel()).cuda()
     advance()
-    got = st.f[:, idx].cpu().numpy()
+    got = st.f[:, torch.from_numpy(cells).cuda()].cpu().numpy()
     ident = ((np.arange(1, 19, dtype=np.uint64)[:, None] * k + np.arange(k, dtype=np.uint64)[None, :])
              .astype(np.uint32))
-    orc = np.zeros_like(gath)
-    O.step(oracle_params(prm), ident, np.ascontiguousarray(gath), orc)
-    assert S >= lat.n_fluid
+    orc = np.zeros_like(vals)
+    O.step(oracle_params(prm), ident, np.ascontiguousarray(vals), orc)
     return rel_err_f64(got, orc)
 
 
 def test_full_size_tube_sampled_step():
     """The full 256^3 tube in the benchmark's launch configuration (sweep over
     16-bit codes, row stride 2^23 + 1024, nontemporal stores, XCD chunk 1):
-    after 20 GPU steps from a random state, one more GPU step is compared on
-    sampled cell ranges (head, middle, ragged tail) with the oracle's step of
-    the same input state; the whole state conserves mass."""
+    one GPU step from a seeded state compared on sampled cell ranges (head,
+    middle, ragged tail) with the oracle; then 20 more steps conserve mass."""
     g = I.packing_tube(2)
     lat = L.build(dev_flags(g), g.periodic, "lex", stride=8389632)
+    sp = O.build(g.flags, g.periodic, "lex", stride=lat.stride)
     n = lat.n_fluid
+    assert n == sp.n_fluid
     prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), "f64", nontemporal=True, xcd_chunk=1)
     print_case("tube full size", n)
     comp = L.compress(lat)
     st = L.init(lat, prm)
-    st.f.copy_(torch.from_numpy(random_state(n, 10, stride=lat.stride)))
-    L.step_c16(st, comp, 20)
-    mass0 = float(st.f[:, :n].sum())
     ranges = [(0, 4096), (n // 3, n // 3 + 3000), (n // 2 + 17, n // 2 + 5000), (n - 2049, n)]
-    err = sampled_step_vs_oracle(lat, prm, st, lambda: L.step_c16(st, comp, 1), ranges)
+    err = sampled_step_vs_oracle(lat, sp, prm, st, lambda: L.step_c16(st, comp, 1), ranges, 10)
     assert err <= TOL_F64
+    mass0 = float(st.f[:, :n].sum())
+    L.step_c16(st, comp, 20)
     assert abs(float(st.f[:, :n].sum()) - mass0) <= 1e-12 * mass0
 
 
 def test_large_packing_full_size_sampled_step():
-    """The 512x512x1024 packing (107 M cells) at full size: 10 GPU steps over
-    16-bit codes from a random state, then one more step compared on sampled
-    ranges with the oracle."""
+    """The 512x512x1024 packing (107 M cells) at full size: one GPU step over
+    16-bit codes from a seeded state, compared on sampled ranges with the
+    oracle (whose sparse representation of the whole box is built on the
+    host)."""
     g = I.workload("large_packing")
     lat = L.build(dev_flags(g), g.periodic, "lex")
     n = lat.n_fluid
     print_case("large packing full size", n)
+    sp = O.build(g.flags, g.periodic, "lex", stride=lat.stride)
+    assert sp.n_fluid == n
     prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), "f64", nontemporal=True, xcd_chunk=64)
     comp = L.compress(lat)
     st = L.init(lat, prm)
-    gen = torch.Generator(device="cuda").manual_seed(11)
-    w = torch.from_numpy(W).cuda()[:, None]
-    st.f[:, :n] = w * (1.0 + 0.02 * torch.randn((19, n), dtype=torch.float64, device="cuda",
-                                                 generator=gen))
-    L.step_c16(st, comp, 10)
     ranges = [(0, 4096), (n // 2, n // 2 + 4096), (n - 3001, n)]
-    err = sampled_step_vs_oracle(lat, prm, st, lambda: L.step_c16(st, comp, 1), ranges)
+    err = sampled_step_vs_oracle(lat, sp, prm, st, lambda: L.step_c16(st, comp, 1), ranges, 11)
     assert err <= TOL_F64
-    del st, comp, lat
+    del st, comp, lat, sp
     torch.cuda.empty_cache()
 
 
