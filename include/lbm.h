@@ -229,6 +229,8 @@ lbm_status lbm_step(const lbm_params* p, int32_t n_params, const lbm_segment* se
  *  ns       solid fraction [stride] or NULL (then grad_ns is ignored).
  *  lam_next double [19][stride] or NULL; lam_t double [19][stride] (output).
  *  grad_ns  double [stride], accumulated (+=); caller zeroes it.
+ *  p->flags the sweep's launch options apply (nontemporal stores of lam_t,
+ *           workgroup-to-XCD mapping); results do not depend on them.
  * Errors: LBM_EINVAL (NULL p/adj/f_t/lam_t, n <= 0, stride < n, storage not
  * FP64), LBM_EOVERFLOW, LBM_EHIP.
  */
