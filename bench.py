@@ -93,7 +93,7 @@ def parse():
                     help="consecutive tiles per XCD for --layout given (0 = one eighth each)")
     ap.add_argument("--experiment", default="headline",
                     choices=["headline", "precision", "adjoint", "batched", "orderings",
-                             "partitions", "ordering_tuner", "compressed", "oracle_rates", "pbb"],
+                             "partitions", "ordering_tuner", "compressed", "oracle_rates", "pbb", "launch_overhead"],
                     help="headline: the JSON line below; the others print one JSON line per "
                          "configuration (see the module docstring)")
     ap.add_argument("--scale", type=int, default=1,

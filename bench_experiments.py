@@ -585,3 +585,37 @@ def pbb(a):
                   "sweeps": sweeps, "layout": [lay.stride, lay.nontemporal, lay.xcd_chunk], **res})
             del lat, comp, ns
             torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------------------
+def launch_overhead(a):
+    """Where the persistent launch pays: geometries small enough that a sweep
+    takes about as long as launching it (the 32^3 packing, 17 k cells) up to
+    the tube (7.8 M cells); one launch per step vs one persistent launch."""
+    cases = [("small_packing", I.packing_small(1), 4000),
+             ("packing_64", I.packing_small(1, n=64, radius=8.0), 2000),
+             ("packing_128", I.packing_small(1, n=128, radius=16.0), 1000),
+             ("tube_packing", I.packing_tube(2), 200)]
+    for name, g, steps in cases:
+        flags = dev_flags(g)
+        lat = L.build(flags, g.periodic, "lex")
+        n = lat.n_fluid
+        for storage in ("f64", "f32"):
+            prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), storage, nontemporal=True, xcd_chunk=1)
+            a1 = L.init(lat, prm)
+            L.step(a1, 10)
+            t_step, _ = timed(lambda: L.step(a1, steps))
+            a2 = L.init(lat, prm)
+            L.step(a2, 10, persistent=True)
+            t_pers, _ = timed(lambda: L.step(a2, steps, persistent=True))
+            emit({"experiment": "launch_overhead", "workload": name, "n_fluid": n,
+                  "storage": storage, "steps": steps,
+                  "us_per_step_launch": round(t_step / steps * 1e6, 2),
+                  "us_per_step_persistent": round(t_pers / steps * 1e6, 2),
+                  "mflups_launch": round(n * steps / t_step / 1e6, 1),
+                  "mflups_persistent": round(n * steps / t_pers / 1e6, 1),
+                  "persistent_speedup": round(t_step / t_pers, 3),
+                  "equal": bool(torch.equal(a1.f[:, :n], a2.f[:, :n]))})
+            del a1, a2
+        del lat
+        torch.cuda.empty_cache()
