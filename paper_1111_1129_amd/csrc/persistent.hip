@@ -30,7 +30,7 @@
 namespace lbm {
 
 constexpr int kPBlock = 256;
-constexpr long kSpinLimit = 1L << 24;  // polls with s_sleep; seconds, far above any step
+constexpr long kSpinLimit = 1L << 27;  // polls of ~256 clocks: ~14 s, far above any step
 
 // workspace layout (uint32 words): [0] global count, [1] error flag,
 // [8..16) per-XCD arrivals, [16..24) per-XCD workgroup counts
@@ -49,7 +49,7 @@ __device__ __forceinline__ int xcc_id() {
 __device__ bool wait_at_least(unsigned int* cnt, unsigned int target, int* err) {
     long spins = 0;
     while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-        __builtin_amdgcn_s_sleep(64);
+        __builtin_amdgcn_s_sleep(4);  // 4 x 64 clocks between polls
         if (++spins > kSpinLimit ||
             __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
             __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
