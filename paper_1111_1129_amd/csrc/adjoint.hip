@@ -37,7 +37,7 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(const double* __restrict_
     uint32_t A[Q];
     A[0] = uint32_t(m);
 #pragma unroll
-    for (int k = 0; k < Q - 1; ++k) A[k + 1] = adj[k * stride + m];
+    for (int k = 0; k < Q - 1; ++k) A[k + 1] = ld_stream(adj + k * stride + m);
     double g[Q], mu[Q], fs[Q];
 #pragma unroll
     for (int k = 0; k < Q; ++k) g[k] = f_t[A[k]];

@@ -125,7 +125,7 @@ __device__ __forceinline__ void update_cell_c16(const typename Storage<ST>::T* _
     int32_t cd[Q - 1];
     const int16_t* cp = codes + m;
 #pragma unroll
-    for (int k = 0; k < Q - 1; ++k) cd[k] = cp[k * stride];
+    for (int k = 0; k < Q - 1; ++k) cd[k] = ld_stream(cp + k * stride);
     const uint32_t S = uint32_t(stride);
     const uint32_t mm = uint32_t(m);
     A g[Q];

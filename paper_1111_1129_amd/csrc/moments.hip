@@ -61,7 +61,7 @@ __global__ __launch_bounds__(kMomBlock) void k_moments(const typename Storage<ST
         // flight at once
         uint32_t a[Q - 1];
 #pragma unroll
-        for (int k = 0; k < Q - 1; ++k) a[k] = adj[k * stride + m];
+        for (int k = 0; k < Q - 1; ++k) a[k] = ld_stream(adj + k * stride + m);
         double g[Q];
         g[0] = static_cast<double>(f[m]);
 #pragma unroll
