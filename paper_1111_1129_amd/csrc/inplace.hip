@@ -116,7 +116,7 @@ __global__ __launch_bounds__(kIBlock) void k_local(typename Storage<ST>::T* f,
     T* fp = f + m;
     A g[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) g[i] = ld<T, A>(fp + opp(i) * stride);
+    for (int i = 0; i < Q; ++i) g[i] = static_cast<A>(ld_stream(fp + opp(i) * stride));  // own column only
     A sf = A(0);
     if constexpr (PBB) sf = static_cast<A>(ns[m]);
     A out[Q];
