@@ -42,7 +42,7 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(const double* __restrict_
 #pragma unroll
     for (int k = 0; k < Q; ++k) g[k] = f_t[A[k]];
 #pragma unroll
-    for (int k = 0; k < Q; ++k) mu[k] = lam_next[k * stride + m];
+    for (int k = 0; k < Q; ++k) mu[k] = ld_stream(lam_next + k * stride + m);  // own column, read once
     trt_collide<double, false>(g, fs, c, 0.0);
     const CellMoments<double> cm = cell_moments(g);
     const double s = PBB ? ns[m] : 0.0;
