@@ -14,28 +14,36 @@ from __future__ import annotations
 import torch
 
 from . import _native as N
-from .lattice import Lattice, init, moments, step
+from .lattice import Compressed, Lattice, compress, init, moments, step_c16
 
 
-def forward_states(lat: Lattice, prm, ns: torch.Tensor, T: int, k: int):
-    """Run T steps from rest; return (J, checkpoints at 0, k, 2k, ..., final state)."""
+def forward_states(lat: Lattice, prm, ns: torch.Tensor, T: int, k: int,
+                   comp: Compressed | None = None):
+    """Run T steps from rest; return (J, checkpoints at 0, k, 2k, ..., final state).
+
+    The sweeps read the 16-bit adjacency codes (bitwise the same states as
+    the sweep over the full list, fewer bytes)."""
+    comp = compress(lat) if comp is None else comp
     st = init(lat, prm, ns=ns)
     ckpts = []
     t = 0
     while t < T:
         ckpts.append(st.f.clone())
         n = min(k, T - t)
-        step(st, n)
+        step_c16(st, comp, n)
         t += n
     _, _, totals = moments(st, fields=False)
     J = totals[0, 1] / lat.n_fluid
     return J, ckpts, st
 
 
-def adjoint_gradient(lat: Lattice, prm, ns: torch.Tensor, T: int, k: int, ckpts=None):
-    """dJ/dns [stride] (float64) by checkpointed reverse sweeps."""
+def adjoint_gradient(lat: Lattice, prm, ns: torch.Tensor, T: int, k: int, ckpts=None,
+                     comp: Compressed | None = None):
+    """dJ/dns [stride] (float64) by checkpointed reverse sweeps (the segment
+    recomputation sweeps over the 16-bit adjacency codes)."""
+    comp = compress(lat) if comp is None else comp
     if ckpts is None:
-        _, ckpts, _ = forward_states(lat, prm, ns, T, k)
+        _, ckpts, _ = forward_states(lat, prm, ns, T, k, comp)
     S, n = lat.stride, lat.n_fluid
     dev = lat.device
     lam = torch.empty((19, S), dtype=torch.float64, device=dev)
@@ -49,8 +57,9 @@ def adjoint_gradient(lat: Lattice, prm, ns: torch.Tensor, T: int, k: int, ckpts=
         t1 = min(t0 + k, T)
         buf[0].copy_(ckpts[s])
         for j in range(1, t1 - t0):
-            st, _ = N.lbm_step(prm, n, S, lat.adj, ns, buf[j - 1], buf[j], 1)
-            N._check("lbm_step", st)
+            st = N.lbm_step_c16(prm, n, S, comp.codes, comp.tile_records, lat.adj, ns,
+                                buf[j - 1], buf[j], 1)
+            N._check("lbm_step_c16", st)
         for t in range(t1 - 1, t0 - 1, -1):
             rc = N.lbm_step_adjoint(prm, n, S, lat.adj, buf[t - t0], ns, lam, lam_prev, grad)
             N._check("lbm_step_adjoint", rc)
