@@ -80,9 +80,10 @@ def parse():
     ap.add_argument("--order", default="lex")
     ap.add_argument("--param", type=int, default=0)
     ap.add_argument("--storage", default="f64", choices=list(BYTES_PER_FLUP))
-    ap.add_argument("--sweep", default="c16", choices=list(SWEEP_KERNELS),
+    ap.add_argument("--sweep", default="c16", choices=list(SWEEP_KERNELS) + ["auto"],
                     help="full: two arrays, uint32 adjacency; c16: two arrays, 16-bit codes; "
-                         "inplace / inplace_c16: one PDF array")
+                         "inplace / inplace_c16: one PDF array; auto: the fastest of the four "
+                         "on this geometry (tuned before the timed region, with --layout tuned)")
     ap.add_argument("--layout", default="tuned", choices=["tuned", "aligned", "given"],
                     help="tuned: time candidate row strides / store policies on the geometry "
                          "first (excluded from the timed region); aligned: 128-byte aligned "
@@ -182,9 +183,21 @@ def main():
     dev = torch.device("cuda:0")
     geom, desc = make_workload(a.workload)
     flags = torch.from_numpy(np.ascontiguousarray(geom.flags)).to(dev)
+    lay = None
+    if a.sweep == "auto":
+        if a.layout != "tuned":
+            print(json.dumps({"error": "--sweep auto needs --layout tuned"}))
+            sys.exit(2)
+        from paper_1111_1129_amd.tune import tune_sweep
+        kind, lay, rates = tune_sweep(flags, geom.periodic, a.order, a.param, a.storage)
+        if kind.startswith("inplace") and a.sweeps % 2:  # needs an even sweep count
+            kind, lay = max(("c16", "full"), key=lambda k: rates.get(k, 0.0)), None
+        print("sweep kinds (MFLUPS): %s -> %s" % (rates, kind), file=sys.stderr)
+        a.sweep = kind
     if a.layout == "tuned":
         from paper_1111_1129_amd.tune import tune_layout
-        lay = tune_layout(flags, geom.periodic, a.order, a.param, a.storage, sweep=a.sweep)
+        if lay is None:
+            lay = tune_layout(flags, geom.periodic, a.order, a.param, a.storage, sweep=a.sweep)
         stride, nt, chunk = lay.stride, lay.nontemporal, lay.xcd_chunk
         for row in lay.table:
             print("tune stride=%d nt=%d chunk=%d: %.0f MFLUPS" % row, file=sys.stderr)
@@ -245,7 +258,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": a.storage,
+        "dtype": "f64" if a.storage.startswith("f64") else "f32",  # arithmetic type
         "data": "synthetic",
         "config": {"workload": f"{a.workload}: {desc}", "n_fluid": n_fluid,
                    "sweeps_per_step": a.sweeps, "order": a.order, "order_param": a.param,

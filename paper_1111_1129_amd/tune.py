@@ -126,6 +126,25 @@ def tune_layout(flags: torch.Tensor, periodic: int, order: str = "lex", param: i
     return best
 
 
+def tune_sweep(flags: torch.Tensor, periodic: int, order: str = "lex", param: int = 0,
+               storage: str = "f64", force=(1e-6, 0.0, 0.0), sweeps: int = 6,
+               kinds=SWEEPS, candidates: list[int] | None = None):
+    """Pick the sweep kind (full list, 16-bit codes, in place, in place over
+    codes) and its layout: each kind's layout is tuned, and the fastest kind
+    wins.  Which one that is depends on the storage form and the ordering
+    (codes pay off where tiles are escape-free; in place where the PDF bytes
+    dominate).  Returns (kind, Layout, {kind: MFLUPS})."""
+    rates = {}
+    best = None
+    for kind in kinds:
+        lay = tune_layout(flags, periodic, order, param, storage, force, sweeps=sweeps,
+                          candidates=candidates, sweep=kind)
+        rates[kind] = round(lay.mflups, 1)
+        if best is None or lay.mflups > best[1].mflups:
+            best = (kind, lay)
+    return best[0], best[1], rates
+
+
 ORDER_CANDIDATES = (("lex", 0), ("blocked", 8), ("blocked", 16), ("blocked", 32),
                     ("blocked", 64), ("morton2", 0), ("hilbert", 0))
 

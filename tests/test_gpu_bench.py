@@ -33,3 +33,16 @@ def test_bench_json_contract(sweep):
     assert r["frac"] == pytest.approx(r["achieved"] / r["peak"], abs=1e-4)
     c = d["cpu_baseline"]
     assert c["kind"] == "oracle" and c["value"] > 0 and c["cores"] >= 1
+
+
+def test_bench_sweep_auto_picks_a_kind():
+    cmd = [sys.executable, os.path.join(ROOT, "bench.py"), "--workload", "small_packing",
+           "--storage", "f16s", "--sweep", "auto", "--steps", "1", "--warmup", "0",
+           "--sweeps", "20", "--cpu-seconds", "0"]
+    print("CASE bench auto", flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True, timeout=300)
+    assert res.returncode == 0, res.stderr[-2000:]
+    d = json.loads(res.stdout.strip().splitlines()[-1])
+    assert d["config"]["sweep"] in ("full", "c16", "inplace", "inplace_c16")
+    assert "sweep kinds (MFLUPS)" in res.stderr
+    assert d["cpu_baseline"] is None
