@@ -432,8 +432,11 @@ def compressed(a):
     results after the same (even) number of sweeps."""
     sweeps = 400
     kinds = ("full", "c16", "inplace", "inplace_c16")
-    cases = [("tube_packing", I.packing_tube(2), "lex", 0),
-             ("tube_packing", I.packing_tube(2), "morton2", 0),
+    tube = I.packing_tube(2)
+    cases = [("tube_packing", tube, "lex", 0),
+             ("tube_packing", tube, "blocked", 16),
+             ("tube_packing", tube, "morton2", 0),
+             ("tube_packing", tube, "hilbert", 0),
              (f"large_packing/{a.scale}", I.workload("large_packing", scale=a.scale), "lex", 0)]
     for name, g, order, param in cases:
         flags = dev_flags(g)
