@@ -285,7 +285,7 @@ lbm_status lbm_partition_stats(int64_t n, int64_t stride, const uint32_t* adj, i
 /*
  * lbm_compress_adjacency -- 16-bit re-encoding of the adjacency list
  * (byte reduction of the sweep over the sparse representation of Sec. 2,
- * whose adjacency list is read by every pull update of Sec. 5: in FP64 it
+ * whose adjacency list is read by every pull update of Sec. 7: in FP64 it
  * is 72 of the 376 bytes an update moves).
  *
  * List tiles are 256 consecutive cells.  Per tile t and direction i = k + 1
@@ -331,7 +331,7 @@ lbm_status lbm_step_c16(const lbm_params* p, int64_t n, int64_t stride, const in
 
 /*
  * lbm_step_inplace -- n_steps TRT pull sweeps on ONE PDF array (halves the
- * PDF memory of lbm_step's two arrays; the sweep of Sec. 5 on the sparse
+ * PDF memory of lbm_step's two arrays; the sweep of Sec. 7 on the sparse
  * representation of Sec. 2).
  *
  * Two kinds of step alternate.  Phase 0 ("layout P", the layout lbm_init and
