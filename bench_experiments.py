@@ -141,6 +141,14 @@ def precision_vs_oracle(a, scale=4, sweeps=500):
                                "sample": f"{sweeps} FP64 sweeps of the {n}-cell crop"}})
 
 
+# Algorithmic bytes of one adjoint cell-step: f^t gathered (19 x 8),
+# lambda^{t+1} read (19 x 8), lambda^t scattered (19 x 8), the solid fraction
+# (8), the gradient read and written (16), plus the adjacency: 18 uint32, or
+# 18 int16 codes and one 80-byte record per 256 cells.
+ADJ_BYTES_FULL = 3 * 152 + 8 + 16 + 72
+ADJ_BYTES_C16 = 3 * 152 + 8 + 16 + 36 + 80 / 256
+
+
 # ---------------------------------------------------------------------------
 def adjoint(a):
     """Gradient of the mean flux w.r.t. the PBB solid fraction: adjoint with
@@ -148,12 +156,14 @@ def adjoint(a):
     n_edge = 128 // a.scale
     g = I.pbb_box(4, n=n_edge)
     flags = dev_flags(g)
-    # layout of the adjoint kernel: row stride x store policy x XCD mapping,
-    # each timed over 20 adjoint steps; the fastest is used for the run
+    # layout of the adjoint kernel (over the 16-bit codes, as the gradient
+    # uses it): row stride x store policy x XCD mapping, each timed over 20
+    # adjoint steps; the fastest is used for the run
     n = L.count_fluid(flags, g.periodic, "lex")
     table = []
     for S in sorted({L.aligned_stride(n), candidate_strides(n)[-2]}):
         lat = L.build(flags, g.periodic, "lex", stride=S)
+        comp = L.compress(lat)
         nsl = torch.zeros(S, dtype=torch.float64, device="cuda")
         nsl[:n] = 0.5
         for nt in (False, True):
@@ -163,14 +173,19 @@ def adjoint(a):
                 lam = torch.zeros((19, S), dtype=torch.float64, device="cuda")
                 lam2 = torch.empty_like(lam)
                 gr = torch.zeros(S, dtype=torch.float64, device="cuda")
-                N.lbm_step_adjoint(prm, n, S, lat.adj, st.f, nsl, lam, lam2, gr)
-                t, _ = timed(lambda: [N.lbm_step_adjoint(prm, n, S, lat.adj, st.f, nsl, lam, lam2, gr)
-                                      for _ in range(20)])
+
+                def adj_steps(reps):
+                    for _ in range(reps):
+                        N.lbm_step_adjoint_c16(prm, n, S, comp.codes, comp.tile_records, lat.adj,
+                                               st.f, nsl, lam, lam2, gr)
+                adj_steps(1)
+                t, _ = timed(lambda: adj_steps(20))
                 table.append((S, nt, chunk, round(t / 20 * 1e6, 1)))
                 del st, lam, lam2, gr
-        del lat
+        del lat, comp
     S_best, nt_best, chunk_best, _ = min(table, key=lambda r: r[3])
     lat = L.build(flags, g.periodic, "lex", stride=S_best)
+    comp = L.compress(lat)
     n, S = lat.n_fluid, lat.stride
     cell = lat.cell_of.cpu().numpy()
     ns_host = np.zeros(S)
@@ -178,17 +193,28 @@ def adjoint(a):
     ns = torch.from_numpy(ns_host).cuda()
     prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), "f64s", nontemporal=nt_best, xcd_chunk=chunk_best)
     T, k = 500, 22
-    t_fwd, (J, ckpts, _) = timed(lambda: AD.forward_states(lat, prm, ns, T, k))
-    t_bwd, grad = timed(lambda: AD.adjoint_gradient(lat, prm, ns, T, k, ckpts))
+    t_fwd, (J, ckpts, _) = timed(lambda: AD.forward_states(lat, prm, ns, T, k, comp))
+    t_bwd, grad = timed(lambda: AD.adjoint_gradient(lat, prm, ns, T, k, ckpts, comp))
     grad = grad.cpu().numpy()[:n]
-    # adjoint kernel alone
+    # adjoint kernel alone, over the codes and over the full list
     lam = torch.zeros((19, S), dtype=torch.float64, device="cuda")
     lam2 = torch.empty_like(lam)
     gr = torch.zeros(S, dtype=torch.float64, device="cuda")
-    N.lbm_step_adjoint(prm, n, S, lat.adj, ckpts[0], ns, lam, lam2, gr)
-    t_adj, _ = timed(lambda: [N.lbm_step_adjoint(prm, n, S, lat.adj, ckpts[0], ns, lam, lam2, gr)
-                              for _ in range(20)])
+
+    def c16_steps(reps):
+        for _ in range(reps):
+            N.lbm_step_adjoint_c16(prm, n, S, comp.codes, comp.tile_records, lat.adj, ckpts[0],
+                                   ns, lam, lam2, gr)
+
+    def full_steps(reps):
+        for _ in range(reps):
+            N.lbm_step_adjoint(prm, n, S, lat.adj, ckpts[0], ns, lam, lam2, gr)
+    c16_steps(1)
+    t_adj, _ = timed(lambda: c16_steps(20))
     t_adj /= 20
+    full_steps(1)
+    t_adj_full, _ = timed(lambda: full_steps(20))
+    t_adj_full /= 20
     del ckpts
     torch.cuda.empty_cache()
 
@@ -249,8 +275,11 @@ def adjoint(a):
           "backward_s": round(t_bwd, 4), "backward_over_forward": round(t_bwd / t_fwd, 2),
           "layout": [S, nt_best, chunk_best], "layout_table_us": table,
           "adjoint_step_us": round(t_adj * 1e6, 1),
-          "adjoint_gbs": round(552 * n / t_adj / 1e9, 1),
-          "adjoint_hbm_frac": round(552 * n / t_adj / 1e9 / PEAK, 4),
+          "adjoint_bytes_per_cell": ADJ_BYTES_C16,
+          "adjoint_gbs": round(ADJ_BYTES_C16 * n / t_adj / 1e9, 1),
+          "adjoint_hbm_frac": round(ADJ_BYTES_C16 * n / t_adj / 1e9 / PEAK, 4),
+          "adjoint_full_list_step_us": round(t_adj_full * 1e6, 1),
+          "adjoint_full_list_gbs": round(ADJ_BYTES_FULL * n / t_adj_full / 1e9, 1),
           "fd_cells": 32, "fd_h": 1e-4, "fd_rel_err_max": float(errs.max()),
           "fd_rel_err_median": float(np.median(errs)), "fd_pass_1e-6": int((errs <= 1e-6).sum()),
           "fd_by_h": {str(h): {"max": float(v.max()), "median": float(np.median(v)),

@@ -239,6 +239,24 @@ lbm_status lbm_step_adjoint(const lbm_params* p, int64_t n, int64_t stride, cons
                             double* lam_t, double* grad_ns, void* stream);
 
 /*
+ * lbm_step_adjoint_c16 -- lbm_step_adjoint (lam_next != NULL) with the slots
+ * rebuilt from the 16-bit codes of lbm_compress_adjacency instead of read
+ * from adj (552 - 36 bytes per cell-step); tiles with escape codes read adj.
+ * Results are bitwise those of lbm_step_adjoint.
+ *
+ *  codes, tile_records  from lbm_compress_adjacency for the same n, stride
+ *        and adj.  The other arguments as lbm_step_adjoint; the seed
+ *        (lam_next == NULL) is not offered here.
+ * Errors: LBM_EINVAL (NULL p/codes/tile_records/adj/f_t/lam_next/lam_t,
+ * n <= 0, stride < n, storage not FP64), LBM_EOVERFLOW, LBM_EHIP.
+ */
+lbm_status lbm_step_adjoint_c16(const lbm_params* p, int64_t n, int64_t stride,
+                                const int16_t* codes, const int32_t* tile_records,
+                                const uint32_t* adj, const void* f_t, const double* ns,
+                                const double* lam_next, double* lam_t, double* grad_ns,
+                                void* stream);
+
+/*
  * lbm_moments -- macroscopic fields and FP64 totals of a stored state.
  *
  * Per list cell, from the populations it gathers through adj (the values the

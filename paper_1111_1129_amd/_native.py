@@ -27,7 +27,7 @@ FLAG_XCD_CHUNK_SHIFT = 8
 
 ENTRY_POINTS = ("lbm_build_adjacency", "lbm_init", "lbm_step", "lbm_step_adjoint",
                 "lbm_moments", "lbm_partition_stats", "lbm_compress_adjacency", "lbm_step_c16",
-                "lbm_step_inplace", "lbm_version", "lbm_status_string")
+                "lbm_step_inplace", "lbm_step_adjoint_c16", "lbm_version", "lbm_status_string")
 
 
 class lbm_geom(C.Structure):
@@ -90,6 +90,9 @@ def load(path: str = LIB_PATH):
         lib.lbm_step_inplace.restype = I32
         lib.lbm_step_inplace.argtypes = [C.POINTER(lbm_params), I64, I64, P, P, P, P, P, I32, I32,
                                          P]
+        lib.lbm_step_adjoint_c16.restype = I32
+        lib.lbm_step_adjoint_c16.argtypes = [C.POINTER(lbm_params), I64, I64, P, P, P, P, P, P,
+                                             P, P, P]
         lib.lbm_version.restype = I32
         lib.lbm_version.argtypes = []
         lib.lbm_status_string.restype = C.c_char_p
@@ -224,6 +227,14 @@ def lbm_step_inplace(params: lbm_params, n, stride, adj, codes, tile_records, ns
     return load().lbm_step_inplace(C.byref(params), n, stride, _ptr(adj), _ptr(codes),
                                    _ptr(tile_records), _ptr(ns), _ptr(f), int(phase),
                                    int(n_steps), _stream(stream))
+
+
+def lbm_step_adjoint_c16(params: lbm_params, n, stride, codes, tile_records, adj, f_t, ns,
+                         lam_next, lam_t, grad_ns, stream=None):
+    return load().lbm_step_adjoint_c16(C.byref(params), n, stride, _ptr(codes),
+                                       _ptr(tile_records), _ptr(adj), _ptr(f_t), _ptr(ns),
+                                       _ptr(lam_next), _ptr(lam_t), _ptr(grad_ns),
+                                       _stream(stream))
 
 
 def lbm_version() -> int:

@@ -40,7 +40,7 @@ def forward_states(lat: Lattice, prm, ns: torch.Tensor, T: int, k: int,
 def adjoint_gradient(lat: Lattice, prm, ns: torch.Tensor, T: int, k: int, ckpts=None,
                      comp: Compressed | None = None):
     """dJ/dns [stride] (float64) by checkpointed reverse sweeps (the segment
-    recomputation sweeps over the 16-bit adjacency codes)."""
+    recomputation and the adjoint steps read the 16-bit adjacency codes)."""
     comp = compress(lat) if comp is None else comp
     if ckpts is None:
         _, ckpts, _ = forward_states(lat, prm, ns, T, k, comp)
@@ -61,8 +61,9 @@ def adjoint_gradient(lat: Lattice, prm, ns: torch.Tensor, T: int, k: int, ckpts=
                                 buf[j - 1], buf[j], 1)
             N._check("lbm_step_c16", st)
         for t in range(t1 - 1, t0 - 1, -1):
-            rc = N.lbm_step_adjoint(prm, n, S, lat.adj, buf[t - t0], ns, lam, lam_prev, grad)
-            N._check("lbm_step_adjoint", rc)
+            rc = N.lbm_step_adjoint_c16(prm, n, S, comp.codes, comp.tile_records, lat.adj,
+                                        buf[t - t0], ns, lam, lam_prev, grad)
+            N._check("lbm_step_adjoint_c16", rc)
             lam, lam_prev = lam_prev, lam
     return grad
 

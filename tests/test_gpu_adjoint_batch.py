@@ -83,6 +83,41 @@ def test_adjoint_launch_options_are_bitwise_identical():
         assert torch.equal(lt, outs[0][0]) and torch.equal(gr, outs[0][1])
 
 
+@pytest.mark.parametrize("order", ["lex", "random"])
+def test_adjoint_over_codes_is_bitwise_the_adjoint(order):
+    """The adjoint step reading 16-bit codes (escape tiles fall back to the
+    full list; the random order escapes almost everywhere) equals the plain
+    adjoint step bit for bit."""
+    g = I.pbb_box(4, n=64)
+    print_case("adjoint c16", order, "pbb_box 64^3")
+    lat = L.build(dev_flags(g), g.periodic, order, 5 if order == "random" else 0)
+    n, S = lat.n_fluid, lat.stride
+    comp = L.compress(lat)
+    if order == "random":
+        assert comp.n_escapes > 0
+    ns = torch.zeros(S, dtype=torch.float64, device="cuda")
+    ns[:n] = torch.from_numpy(g.ns.ravel()[lat.cell_of.cpu().numpy()]).cuda()
+    f = torch.from_numpy(random_state(n, 3, amp=1e-3, shifted=True, stride=S)).cuda()
+    lam = torch.zeros((19, S), dtype=torch.float64, device="cuda")
+    lam[:, :n] = torch.randn((19, n), dtype=torch.float64,
+                             generator=torch.Generator().manual_seed(6)).cuda()
+    prm = L.params(0.8, 3 / 16, (1e-5, 0, 0), "f64s")
+    for sf in (ns, None):  # with and without partial bounce-back
+        outs = []
+        for c16 in (False, True):
+            lt = torch.zeros((19, S), dtype=torch.float64, device="cuda")
+            gr = torch.zeros(S, dtype=torch.float64, device="cuda")
+            if c16:
+                rc = N.lbm_step_adjoint_c16(prm, n, S, comp.codes, comp.tile_records, lat.adj, f,
+                                            sf, lam, lt, gr if sf is not None else None)
+            else:
+                rc = N.lbm_step_adjoint(prm, n, S, lat.adj, f, sf, lam, lt,
+                                        gr if sf is not None else None)
+            assert rc == 0
+            outs.append((lt[:, :n].clone(), gr[:n].clone()))
+        assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+
+
 def test_gradient_vs_oracle_with_checkpoints(pbb):
     g, sp, lat, ns = pbb
     prm = L.params(0.8, 3 / 16, (1e-5, 0, 0), "f64s")
