@@ -10,10 +10,11 @@ whole job (MFLUPS, counting fluid cells only).
 Default workload: 256^3 tube (diameter 240) packed with radius-12 spheres by
 seeded random sequential addition, periodic in x, force-driven, D3Q19 TRT with
 tau+ = 0.8, magic 3/16, 1000 sweeps, FP64 storage, lexicographic ordering.
-The sweep reads the adjacency as 16-bit codes (``--sweep c16``: the codes are
-built inside the step; results are bitwise those of the sweep over the full
-uint32 list, ``--sweep full``); ``inplace`` / ``inplace_c16`` step one PDF
-array instead of two.
+The sweep reads the adjacency as 8-bit codes in the tiles whose codes fit a
+byte and as 16-bit codes elsewhere (``--sweep c8``: the codes are built inside
+the step; results are bitwise those of the sweep over the full uint32 list,
+``--sweep full``); ``c16`` reads 16-bit codes only; ``inplace`` /
+``inplace_c16`` step one PDF array instead of two.
 
 Experiments (``--experiment``, one JSON line per configuration, see
 bench_experiments.py): precision (FP64 / FP32 / shifted FP16 storage on the
@@ -23,12 +24,12 @@ differences), batched (64 uneven geometries, one persistent launch vs one
 launch per step vs separate launches), orderings (lexicographic, blocking
 factors, Z curves, random on the tube), partitions (neighbour chunks and
 remote links of a list cut into G chunks), ordering_tuner, compressed (sweep
-over 16-bit adjacency codes vs the full list).
+over 16-bit and 8-bit adjacency codes vs the full list).
 
 Besides the one JSON line the run reports, for the dominant kernel (the
 sweep), the achieved HBM bandwidth from its algorithmic bytes (19 PDFs read +
-19 written + the adjacency: 18 uint32 entries, or 18 int16 codes and an
-80-byte record per 256 cells, per fluid cell) and its average launch time
+19 written + the adjacency: 18 uint32 entries, or 18 int16 / int8 codes and
+an 80-byte record per 256 cells, per fluid cell) and its average launch time
 measured with HIP events on the launch stream, and a CPU baseline: the plain
 FP64 oracle timed on the host cores on a bounded sample.
 """
@@ -50,18 +51,38 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_FLUP = {"f64": 376, "f64s": 376, "f32": 224, "f32s": 224, "f16s": 148}
 PDF_SIZE = {"f64": 8, "f64s": 8, "f32": 4, "f32s": 4, "f16s": 2}
 SWEEP_KERNELS = {"full": ("k_trt", "trt.hip"), "c16": ("k_trt_c16", "compress.hip"),
+                 "c8": ("k_trt_c8", "compress.hip"),
                  "inplace": ("k_gather_scatter + k_local", "inplace.hip"),
                  "inplace_c16": ("k_gather_scatter + k_local", "inplace.hip")}
 
 
-def sweep_bytes(storage: str, kind: str) -> float:
+def sweep_bytes(storage: str, kind: str, narrow: float = 0.0, escape: float = 0.0) -> float:
     """Algorithmic bytes per cell update: 19 PDF loads + 19 stores, plus the
-    adjacency: 18 uint32 (full list) or 18 int16 codes + an 80-byte tile
-    record per 256 cells (c16); the in-place sweep reads it every other step."""
-    adj = 36 + 80 / 256 if kind.endswith("c16") else 72.0
+    adjacency: 18 uint32 (full list), or per cell of a tile 18 int8 codes
+    (narrow tile, c8 only), 18 int16 codes, or 18 uint32 (tile with escapes),
+    plus an 80-byte tile record per 256 cells.  narrow / escape are the
+    shares of cells in narrow tiles and in tiles with escapes.  The in-place
+    sweep reads the adjacency every other step."""
+    if kind.endswith("c8"):
+        adj = 18 * narrow + 36 * (1 - narrow - escape) + 72 * escape + 80 / 256
+    elif kind.endswith("c16"):
+        adj = 36 * (1 - escape) + 72 * escape + 80 / 256
+    else:
+        adj = 72.0
     if kind.startswith("inplace"):
         adj /= 2
     return 38 * PDF_SIZE[storage] + adj
+
+
+def code_mix(comp) -> tuple[float, float]:
+    """(share of cells in narrow tiles, share in tiles with escapes)."""
+    if comp is None:
+        return 0.0, 0.0
+    rec = comp.tile_records.cpu().numpy()
+    cells = np.full(len(rec), 256, dtype=np.int64)
+    cells[-1] = comp.n - 256 * (len(rec) - 1)
+    narrow = float(cells[rec[:, 19] != 0].sum()) / comp.n if comp.codes8 is not None else 0.0
+    return narrow, float(cells[rec[:, 18] != 0].sum()) / comp.n
 
 
 def kernel_sources(kind: str):
@@ -80,9 +101,10 @@ def parse():
     ap.add_argument("--order", default="lex")
     ap.add_argument("--param", type=int, default=0)
     ap.add_argument("--storage", default="f64", choices=list(BYTES_PER_FLUP))
-    ap.add_argument("--sweep", default="c16", choices=list(SWEEP_KERNELS) + ["auto"],
+    ap.add_argument("--sweep", default="c8", choices=list(SWEEP_KERNELS) + ["auto"],
                     help="full: two arrays, uint32 adjacency; c16: two arrays, 16-bit codes; "
-                         "inplace / inplace_c16: one PDF array; auto: the fastest of the four "
+                         "c8: two arrays, 8-bit codes where a tile allows them, else 16-bit; "
+                         "inplace / inplace_c16: one PDF array; auto: the fastest kind "
                          "on this geometry (tuned before the timed region, with --layout tuned)")
     ap.add_argument("--layout", default="tuned", choices=["tuned", "aligned", "given"],
                     help="tuned: time candidate row strides / store policies on the geometry "
@@ -191,7 +213,7 @@ def main():
         from paper_1111_1129_amd.tune import tune_sweep
         kind, lay, rates = tune_sweep(flags, geom.periodic, a.order, a.param, a.storage)
         if kind.startswith("inplace") and a.sweeps % 2:  # needs an even sweep count
-            kind, lay = max(("c16", "full"), key=lambda k: rates.get(k, 0.0)), None
+            kind, lay = max(("c8", "c16", "full"), key=lambda k: rates.get(k, 0.0)), None
         print("sweep kinds (MFLUPS): %s -> %s" % (rates, kind), file=sys.stderr)
         a.sweep = kind
     if a.layout == "tuned":
@@ -214,7 +236,7 @@ def main():
 
     def one_pass(ev=None):
         lat = L.build(flags, geom.periodic, a.order, a.param, stride=stride)
-        sw = Sweeper(lat, a.sweep)  # builds the 16-bit codes for the c16 kinds
+        sw = Sweeper(lat, a.sweep)  # builds the codes for the c16 / c8 kinds
         st = sw.init(prm)
         if ev is not None:
             ev[0].record(stream)
@@ -222,7 +244,7 @@ def main():
         if ev is not None:
             ev[1].record(stream)
         _, _, totals = L.moments(st, fields=False)
-        return lat, st, totals
+        return lat, sw, totals
 
     for _ in range(a.warmup):
         one_pass()
@@ -232,7 +254,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(a.steps):
-        lat, st, totals = one_pass(events[k])
+        lat, sw, totals = one_pass(events[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     n_fluid = lat.n_fluid
@@ -245,7 +267,8 @@ def main():
 
     flups = n_fluid * a.sweeps * a.steps
     value = flups / wall / 1e6
-    bpf = sweep_bytes(a.storage, a.sweep)
+    narrow, escape = code_mix(sw.comp)
+    bpf = sweep_bytes(a.storage, a.sweep, narrow, escape)
     achieved = bpf * n_fluid / launch_s / 1e9
     line = {
         "metric": METRIC,
@@ -263,6 +286,7 @@ def main():
         "config": {"workload": f"{a.workload}: {desc}", "n_fluid": n_fluid,
                    "sweeps_per_step": a.sweeps, "order": a.order, "order_param": a.param,
                    "storage": a.storage, "sweep": a.sweep,
+                   "code_tiles": {"narrow_cells": round(narrow, 4), "escape_cells": round(escape, 4)},
                    "tau_plus": 0.8, "magic": 0.1875, "force_x": 1e-6,
                    "layout": a.layout, "row_stride": lat.stride, "nontemporal": nt,
                    "xcd_chunk": chunk},

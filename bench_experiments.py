@@ -19,7 +19,7 @@ from paper_1111_1129_amd import inputs as I
 from paper_1111_1129_amd import lattice as L
 from paper_1111_1129_amd.tune import tune_layout, tune_ordering, candidate_strides
 
-from bench import PDF_SIZE, sweep_bytes  # one definition of the per-update byte counts
+from bench import PDF_SIZE, code_mix, sweep_bytes  # one definition of the per-update byte counts
 
 BYTES = {"f64": 376, "f64s": 376, "f32": 224, "f32s": 224, "f16s": 148}
 PEAK = 8000.0
@@ -451,16 +451,17 @@ def ordering_tuner(a):
 def bytes_resident(storage, kind):
     """HBM bytes per cell held by the arrays a sweep needs."""
     pdf = 19 * PDF_SIZE[storage] * (1 if kind.startswith("inplace") else 2)
-    return pdf + 72 + (36 if "c16" in kind else 0)
+    return pdf + 72 + (36 if kind.endswith(("c16", "c8")) else 0) + (18 if kind == "c8" else 0)
 
 
 def compressed(a):
-    """Byte reduction: the sweep over 16-bit adjacency codes and the in-place
-    sweep (one PDF array), each against the two-array sweep over the full
-    uint32 list: speed per storage form and ordering, bitwise equality of the
-    results after the same (even) number of sweeps."""
+    """Byte reduction: the sweep over 16-bit adjacency codes, over 8-bit codes
+    where a tile allows them, and the in-place sweep (one PDF array), each
+    against the two-array sweep over the full uint32 list: speed per storage
+    form and ordering, bitwise equality of the results after the same (even)
+    number of sweeps."""
     sweeps = 400
-    kinds = ("full", "c16", "inplace", "inplace_c16")
+    kinds = ("full", "c16", "c8", "inplace", "inplace_c16")
     tube = I.packing_tube(2)
     cases = [("tube_packing", tube, "lex", 0),
              ("tube_packing", tube, "blocked", 16),
@@ -474,6 +475,8 @@ def compressed(a):
             lat = L.build(flags, g.periodic, order, param, stride=lay.stride)
             n = lat.n_fluid
             t_asm, comp = timed(lambda: L.compress(lat))
+            t_narrow, _ = timed(lambda: L.narrow(comp))  # word 19: read by c8 only
+            narrow, escape = code_mix(comp)
             res = {}
             for kind in kinds:
                 best = None
@@ -481,9 +484,13 @@ def compressed(a):
                                   (True, 0), (False, 0)):
                     prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), storage, nontemporal=nt,
                                    xcd_chunk=chunk)
-                    if kind in ("full", "c16"):
+                    if kind in ("full", "c16", "c8"):
                         def run(k, st):
-                            return L.step(st, k) if kind == "full" else L.step_c16(st, comp, k)
+                            if kind == "full":
+                                return L.step(st, k)
+                            if kind == "c8":
+                                return L.step_c8(st, comp, k)
+                            return L.step_c16(st, comp, k)
                         make = L.init
                     else:
                         def run(k, st):
@@ -501,15 +508,17 @@ def compressed(a):
             tf = res["full"][0]
             rec = {"experiment": "compressed", "workload": name, "order": order, "n_fluid": n,
                    "storage": storage, "sweeps": sweeps, "stride": lat.stride,
-                   "escapes": comp.n_escapes, "compress_ms": round(t_asm * 1e3, 2)}
+                   "escapes": comp.n_escapes, "compress_ms": round(t_asm * 1e3, 2),
+                   "narrow_ms": round(t_narrow * 1e3, 2), "narrow_cells": round(narrow, 4),
+                   "escape_cells": round(escape, 4)}
             for kind in kinds:
                 t, nt, chunk, f = res[kind]
+                bpu = sweep_bytes(storage, kind, narrow, escape)
                 rec[kind] = {"mflups": round(n * sweeps / t / 1e6, 1),
                              "speedup": round(tf / t, 3),
-                             "bytes_per_update": round(sweep_bytes(storage, kind), 2),
-                             "gbs": round(sweep_bytes(storage, kind) * n * sweeps / t / 1e9, 1),
-                             "hbm_frac": round(sweep_bytes(storage, kind) * n * sweeps / t / 1e9
-                                               / PEAK, 4),
+                             "bytes_per_update": round(bpu, 2),
+                             "gbs": round(bpu * n * sweeps / t / 1e9, 1),
+                             "hbm_frac": round(bpu * n * sweeps / t / 1e9 / PEAK, 4),
                              "resident_bytes_per_cell": bytes_resident(storage, kind),
                              "layout": [nt, chunk],
                              "bitwise_equal_full": bool(torch.equal(f, res["full"][3]))}

@@ -348,6 +348,47 @@ lbm_status lbm_step_c16(const lbm_params* p, int64_t n, int64_t stride, const in
                         void* f_a, void* f_b, int32_t n_steps, void* stream);
 
 /*
+ * lbm_narrow_codes -- 8-bit form of the 16-bit codes where a whole tile
+ * allows it (further byte reduction of the adjacency read by the pull
+ * updates of Sec. 7 over the list of Sec. 2).
+ *
+ * A tile (256 cells) is narrow when every code of its live cells is a
+ * bounce-back (-32768) or lies in [-127, 127]; a tile with escapes never is.
+ * For a narrow tile codes8[k * stride + m] = codes[k * stride + m], with
+ * -128 for bounce-back, against the same per-tile offsets, and
+ * tile_records[t * 20 + 19] is set to 1; for any other tile it is set to 0
+ * and its codes8 entries to 0.
+ *
+ *  codes         int16 [18][stride] from lbm_compress_adjacency (input).
+ *  tile_records  int32 [ceil(n / 256) * 20] from the same call (word 19 of
+ *        every record is written).
+ *  codes8        int8  [18][stride] (output; columns >= n untouched).
+ *  n_narrow_tiles (host) number of narrow tiles.
+ *  workspace, ws_bytes  256 bytes of device scratch (query with workspace
+ *        NULL).  The call synchronizes the stream to return n_narrow_tiles.
+ * Errors: LBM_EINVAL (NULL pointers, n <= 0), LBM_EOVERFLOW, LBM_EWORKSPACE,
+ * LBM_EHIP.
+ */
+lbm_status lbm_narrow_codes(int64_t n, int64_t stride, const int16_t* codes,
+                            int32_t* tile_records, int8_t* codes8, int64_t* n_narrow_tiles,
+                            void* workspace, size_t* ws_bytes, void* stream);
+
+/*
+ * lbm_step_c8 -- lbm_step_c16 that reads codes8 in narrow tiles: such a tile
+ * moves 19 * 2 * sizeof(PDF) + 18.3 bytes per cell update.  Other tiles read
+ * the 16-bit codes, tiles with escapes adj.  Results are bitwise equal to
+ * lbm_step's.
+ *
+ *  codes8, codes, tile_records  from lbm_narrow_codes and
+ *        lbm_compress_adjacency for the same n, stride and adj.
+ *  adj, ns, f_a, f_b, n_steps, stream  as lbm_step_c16.
+ * Errors: LBM_EINVAL, LBM_EOVERFLOW, LBM_EHIP.
+ */
+lbm_status lbm_step_c8(const lbm_params* p, int64_t n, int64_t stride, const int8_t* codes8,
+                       const int16_t* codes, const int32_t* tile_records, const uint32_t* adj,
+                       const double* ns, void* f_a, void* f_b, int32_t n_steps, void* stream);
+
+/*
  * lbm_step_inplace -- n_steps TRT pull sweeps on ONE PDF array (halves the
  * PDF memory of lbm_step's two arrays; the sweep of Sec. 7 on the sparse
  * representation of Sec. 2).

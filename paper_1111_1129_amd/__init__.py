@@ -18,8 +18,8 @@ def __getattr__(name):
     # lazy: keep `import paper_1111_1129_amd.inputs` free of torch and HIP
     if name in ("build", "init", "step", "moments", "params", "set_state", "count_fluid",
                 "partition_stats", "aligned_stride", "Lattice", "State", "Batch",
-                "compress", "step_c16", "Compressed", "InplaceState", "init_inplace",
-                "step_inplace"):
+                "compress", "step_c16", "narrow", "step_c8", "Compressed", "InplaceState",
+                "init_inplace", "step_inplace"):
         from . import lattice
         return getattr(lattice, name)
     if name in ("PermeabilityFn", "adjoint_gradient", "forward_states"):
@@ -30,7 +30,8 @@ def __getattr__(name):
         return getattr(tune, name)
     if name in ("lbm_build_adjacency", "lbm_init", "lbm_step", "lbm_step_adjoint", "lbm_moments",
                 "lbm_partition_stats", "lbm_compress_adjacency", "lbm_step_c16",
-                "lbm_step_inplace", "lbm_step_adjoint_c16", "lbm_version",
+                "lbm_step_inplace", "lbm_step_adjoint_c16", "lbm_narrow_codes", "lbm_step_c8",
+                "lbm_version",
                 "LbmError"):
         from . import _native
         return getattr(_native, name)

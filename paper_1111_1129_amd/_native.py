@@ -27,7 +27,8 @@ FLAG_XCD_CHUNK_SHIFT = 8
 
 ENTRY_POINTS = ("lbm_build_adjacency", "lbm_init", "lbm_step", "lbm_step_adjoint",
                 "lbm_moments", "lbm_partition_stats", "lbm_compress_adjacency", "lbm_step_c16",
-                "lbm_step_inplace", "lbm_step_adjoint_c16", "lbm_version", "lbm_status_string")
+                "lbm_step_inplace", "lbm_step_adjoint_c16", "lbm_narrow_codes", "lbm_step_c8",
+                "lbm_version", "lbm_status_string")
 
 
 class lbm_geom(C.Structure):
@@ -93,6 +94,11 @@ def load(path: str = LIB_PATH):
         lib.lbm_step_adjoint_c16.restype = I32
         lib.lbm_step_adjoint_c16.argtypes = [C.POINTER(lbm_params), I64, I64, P, P, P, P, P, P,
                                              P, P, P]
+        lib.lbm_narrow_codes.restype = I32
+        lib.lbm_narrow_codes.argtypes = [I64, I64, P, P, P, C.POINTER(C.c_int64), P,
+                                         C.POINTER(SZ), P]
+        lib.lbm_step_c8.restype = I32
+        lib.lbm_step_c8.argtypes = [C.POINTER(lbm_params), I64, I64, P, P, P, P, P, P, P, I32, P]
         lib.lbm_version.restype = I32
         lib.lbm_version.argtypes = []
         lib.lbm_status_string.restype = C.c_char_p
@@ -220,6 +226,25 @@ def lbm_step_c16(params: lbm_params, n, stride, codes, tile_records, adj, ns, f_
     return load().lbm_step_c16(C.byref(params), n, stride, _ptr(codes), _ptr(tile_records),
                                _ptr(adj), _ptr(ns), _ptr(f_a), _ptr(f_b), int(n_steps),
                                _stream(stream))
+
+
+def lbm_narrow_codes(n, stride, codes, tile_records, codes8, workspace=None, ws_bytes=0,
+                     stream=None, query=False):
+    """Returns (status, n_narrow_tiles, ws_bytes).  Synchronizes the stream."""
+    lib = load()
+    ws = C.c_size_t(ws_bytes)
+    cnt = C.c_int64(0)
+    st = lib.lbm_narrow_codes(n, stride, _ptr(codes), _ptr(tile_records), _ptr(codes8),
+                              C.byref(cnt), None if query else _ptr(workspace), C.byref(ws),
+                              None if query else _stream(stream))
+    return st, cnt.value, ws.value
+
+
+def lbm_step_c8(params: lbm_params, n, stride, codes8, codes, tile_records, adj, ns, f_a, f_b,
+                n_steps, stream=None):
+    return load().lbm_step_c8(C.byref(params), n, stride, _ptr(codes8), _ptr(codes),
+                              _ptr(tile_records), _ptr(adj), _ptr(ns), _ptr(f_a), _ptr(f_b),
+                              int(n_steps), _stream(stream))
 
 
 def lbm_step_inplace(params: lbm_params, n, stride, adj, codes, tile_records, ns, f, phase,

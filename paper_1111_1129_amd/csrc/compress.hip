@@ -17,7 +17,15 @@
 // neither path branches per lane and every gather of a cell is in flight at
 // once.  Results are bit-identical to the uncompressed sweep; the adjacency
 // traffic of an escape-free tile drops from 72 to 36.3 bytes per cell.
+//
+// 8-bit codes (lbm_narrow_codes, lbm_step_c8): in a tile whose 16-bit codes
+// all lie in -127..127 or are bounce-backs (most tiles of a lexicographic
+// order: the offsets of a tile spread over little more than the fluid count
+// of one row) the same codes fit one byte each, with -128 for bounce-back.
+// Word 19 of the tile record marks such a tile; the sweep then reads 18 bytes
+// of codes per cell instead of 36, and the other tiles as before.
 #include <algorithm>
+#include <type_traits>
 
 #include "lbm_device.hpp"
 #include "lbm_host.hpp"
@@ -109,21 +117,56 @@ __global__ __launch_bounds__(kCTile) void k_compress(const uint32_t* __restrict_
 
 __global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
 
-// One cell update of an escape-free tile, the slots rebuilt from the codes in
-// 32-bit arithmetic (every slot is below 19 * stride < 2^32).  The per-tile
-// part i * stride + tile * 256 + toff is uniform (scalar); per lane it adds
-// the lane and the code.
-template <int ST, bool PBB, bool NT>
-__device__ __forceinline__ void update_cell_c16(const typename Storage<ST>::T* __restrict__ src,
-                                                typename Storage<ST>::T* __restrict__ dst,
-                                                const int16_t* __restrict__ codes,
-                                                const int32_t* __restrict__ rec,
-                                                const double* __restrict__ ns, int64_t m,
-                                                int64_t stride, const TrtConst& c) {
+constexpr int8_t kNarrowBounce = -128;
+constexpr int32_t kNarrowMax = 127;
+
+// One workgroup per tile: the tile is narrow if every live cell's 18 codes
+// fit (a tile with escapes never does).  Codes of a wide tile are stored as 0.
+__global__ __launch_bounds__(kCTile) void k_narrow(const int16_t* __restrict__ codes, int64_t n,
+                                                   int64_t stride, int32_t* __restrict__ rec,
+                                                   int8_t* __restrict__ codes8,
+                                                   unsigned long long* __restrict__ narrow_tiles) {
+    const int64_t tile = blockIdx.x;
+    const int64_t m = tile * kCTile + threadIdx.x;
+    const bool live = m < n;
+    const int64_t mc = live ? m : 0;  // lanes past the list read cell 0 and are ignored
+    int32_t cd[Q - 1];
+#pragma unroll
+    for (int k = 0; k < Q - 1; ++k) cd[k] = codes[k * stride + mc];
+    bool fits = true;
+#pragma unroll
+    for (int k = 0; k < Q - 1; ++k)
+        fits = fits && (cd[k] == kCodeBounce || (cd[k] >= -kNarrowMax && cd[k] <= kNarrowMax));
+    const bool narrow = __syncthreads_and(!live || fits) != 0;  // every thread takes part
+    if (live) {
+#pragma unroll
+        for (int k = 0; k < Q - 1; ++k)
+            codes8[k * stride + m] =
+                narrow ? (cd[k] == kCodeBounce ? kNarrowBounce : int8_t(cd[k])) : int8_t(0);
+    }
+    if (threadIdx.x == 0) {
+        rec[tile * kRec + Q] = narrow ? 1 : 0;
+        if (narrow) atomicAdd(narrow_tiles, 1ull);
+    }
+}
+
+// One cell update of an escape-free tile, the slots rebuilt from the 16-bit
+// (CT = int16_t) or 8-bit (int8_t) codes in 32-bit arithmetic (every slot is
+// below 19 * stride < 2^32).  The per-tile part i * stride + tile * 256 + toff
+// is uniform (scalar); per lane it adds the lane and the code.
+template <int ST, bool PBB, bool NT, class CT>
+__device__ __forceinline__ void update_cell_coded(const typename Storage<ST>::T* __restrict__ src,
+                                                  typename Storage<ST>::T* __restrict__ dst,
+                                                  const CT* __restrict__ codes,
+                                                  const int32_t* __restrict__ rec,
+                                                  const double* __restrict__ ns, int64_t m,
+                                                  int64_t stride, const TrtConst& c) {
     using T = typename Storage<ST>::T;
     using A = typename Storage<ST>::A;
+    constexpr int32_t bounce = std::is_same_v<CT, int8_t> ? int32_t(kNarrowBounce)
+                                                          : int32_t(kCodeBounce);
     int32_t cd[Q - 1];
-    const int16_t* cp = codes + m;
+    const CT* cp = codes + m;
 #pragma unroll
     for (int k = 0; k < Q - 1; ++k) cd[k] = ld_stream(cp + k * stride);
     const uint32_t S = uint32_t(stride);
@@ -135,7 +178,7 @@ __device__ __forceinline__ void update_cell_c16(const typename Storage<ST>::T* _
         const uint32_t i = k + 1;
         const uint32_t streamed = i * S + uint32_t(rec[k]) + mm + uint32_t(cd[k]);
         const uint32_t bounced = uint32_t(opp(int(i))) * S + mm;
-        g[i] = ld<T, A>(src + (cd[k] == kCodeBounce ? bounced : streamed));
+        g[i] = ld<T, A>(src + (cd[k] == bounce ? bounced : streamed));
     }
     A sf = A(0);
     if constexpr (PBB) sf = static_cast<A>(ns[m]);
@@ -161,39 +204,79 @@ __global__ __launch_bounds__(kCTile) void k_trt_c16(const typename Storage<ST>::
     if (rec[Q - 1] != 0)
         update_cell<ST, PBB, NT>(src, dst, adj, ns, m, stride, c);
     else
-        update_cell_c16<ST, PBB, NT>(src, dst, codes, rec, ns, m, stride, c);
+        update_cell_coded<ST, PBB, NT, int16_t>(src, dst, codes, rec, ns, m, stride, c);
 }
 
+// Three-way, uniform over the workgroup: narrow tile -> 8-bit codes, tile
+// with escapes -> full list, otherwise 16-bit codes.
 template <int ST, bool PBB, bool NT>
-lbm_status launch_c16(const TrtConst& c, int cs, int64_t n, int64_t stride, const int16_t* codes,
-                      const int32_t* toff, const uint32_t* adj, const double* ns, void* fa,
-                      void* fb, int n_steps, hipStream_t s) {
+__global__ __launch_bounds__(kCTile) void k_trt_c8(const typename Storage<ST>::T* __restrict__ src,
+                                                   typename Storage<ST>::T* __restrict__ dst,
+                                                   const int8_t* __restrict__ codes8,
+                                                   const int16_t* __restrict__ codes,
+                                                   const int32_t* __restrict__ tile_rec,
+                                                   const uint32_t* __restrict__ adj,
+                                                   const double* __restrict__ ns, int64_t n,
+                                                   int64_t stride, TrtConst c, int chunk_shift) {
+    const int64_t tile = logical_block(chunk_shift);
+    const int64_t m = tile * kCTile + threadIdx.x;
+    if (m >= n) return;
+    const int32_t* rec = tile_rec + tile * kRec;
+    if (rec[Q] != 0)
+        update_cell_coded<ST, PBB, NT, int8_t>(src, dst, codes8, rec, ns, m, stride, c);
+    else if (rec[Q - 1] != 0)
+        update_cell<ST, PBB, NT>(src, dst, adj, ns, m, stride, c);
+    else
+        update_cell_coded<ST, PBB, NT, int16_t>(src, dst, codes, rec, ns, m, stride, c);
+}
+
+// codes8 == nullptr: the 16-bit sweep (k_trt_c16); else the 8-bit one.
+template <int ST, bool PBB, bool NT>
+lbm_status launch_coded(const TrtConst& c, int cs, int64_t n, int64_t stride,
+                        const int8_t* codes8, const int16_t* codes, const int32_t* toff,
+                        const uint32_t* adj, const double* ns, void* fa, void* fb, int n_steps,
+                        hipStream_t s) {
     using T = typename Storage<ST>::T;
     T* a = static_cast<T*>(fa);
     T* b = static_cast<T*>(fb);
-    const int64_t grid = grid_blocks(n, kCTile, cs);
+    const dim3 g{unsigned(grid_blocks(n, kCTile, cs))}, blk{unsigned(kCTile)};
     for (int k = 0; k < n_steps; ++k) {
         const T* src = (k & 1) ? b : a;
         T* dst = (k & 1) ? a : b;
-        k_trt_c16<ST, PBB, NT><<<dim3(unsigned(grid)), dim3(kCTile), 0, s>>>(src, dst, codes, toff, adj,
-                                                                            ns, n, stride, c, cs);
+        if (codes8)
+            k_trt_c8<ST, PBB, NT><<<g, blk, 0, s>>>(src, dst, codes8, codes, toff, adj, ns, n, stride, c, cs);
+        else
+            k_trt_c16<ST, PBB, NT><<<g, blk, 0, s>>>(src, dst, codes, toff, adj, ns, n, stride, c, cs);
         if (hipGetLastError() != hipSuccess) return LBM_EHIP;
     }
     return LBM_OK;
 }
 
 template <int ST>
-lbm_status dispatch_c16(const lbm_params& p, int64_t n, int64_t stride, const int16_t* codes,
-                        const int32_t* toff, const uint32_t* adj, const double* ns, void* fa,
-                        void* fb, int n_steps, hipStream_t s) {
+lbm_status dispatch_coded(const lbm_params& p, int64_t n, int64_t stride, const int8_t* codes8,
+                          const int16_t* codes, const int32_t* toff, const uint32_t* adj,
+                          const double* ns, void* fa, void* fb, int n_steps, hipStream_t s) {
     const TrtConst c = make_trt_const(p);
     const int cs = chunk_shift_for(p.flags, n, kCTile);
     const bool nt = p.flags & LBM_FLAG_NONTEMPORAL;
     if (ns)
-        return nt ? launch_c16<ST, true, true>(c, cs, n, stride, codes, toff, adj, ns, fa, fb, n_steps, s)
-                  : launch_c16<ST, true, false>(c, cs, n, stride, codes, toff, adj, ns, fa, fb, n_steps, s);
-    return nt ? launch_c16<ST, false, true>(c, cs, n, stride, codes, toff, adj, ns, fa, fb, n_steps, s)
-              : launch_c16<ST, false, false>(c, cs, n, stride, codes, toff, adj, ns, fa, fb, n_steps, s);
+        return nt ? launch_coded<ST, true, true>(c, cs, n, stride, codes8, codes, toff, adj, ns, fa, fb, n_steps, s)
+                  : launch_coded<ST, true, false>(c, cs, n, stride, codes8, codes, toff, adj, ns, fa, fb, n_steps, s);
+    return nt ? launch_coded<ST, false, true>(c, cs, n, stride, codes8, codes, toff, adj, ns, fa, fb, n_steps, s)
+              : launch_coded<ST, false, false>(c, cs, n, stride, codes8, codes, toff, adj, ns, fa, fb, n_steps, s);
+}
+
+lbm_status step_coded(const lbm_params& p, int64_t n, int64_t stride, const int8_t* codes8,
+                      const int16_t* codes, const int32_t* toff, const uint32_t* adj,
+                      const double* ns, void* fa, void* fb, int n_steps, hipStream_t s) {
+    switch (p.storage) {
+    case LBM_F64: return dispatch_coded<LBM_F64>(p, n, stride, codes8, codes, toff, adj, ns, fa, fb, n_steps, s);
+    case LBM_F64_SHIFTED: return dispatch_coded<LBM_F64_SHIFTED>(p, n, stride, codes8, codes, toff, adj, ns, fa, fb, n_steps, s);
+    case LBM_F32: return dispatch_coded<LBM_F32>(p, n, stride, codes8, codes, toff, adj, ns, fa, fb, n_steps, s);
+    case LBM_F32_SHIFTED: return dispatch_coded<LBM_F32_SHIFTED>(p, n, stride, codes8, codes, toff, adj, ns, fa, fb, n_steps, s);
+    case LBM_F16_SHIFTED: return dispatch_coded<LBM_F16_SHIFTED>(p, n, stride, codes8, codes, toff, adj, ns, fa, fb, n_steps, s);
+    default: return LBM_EINVAL;
+    }
 }
 
 }  // namespace lbm
@@ -235,13 +318,47 @@ extern "C" lbm_status lbm_step_c16(const lbm_params* p, int64_t n, int64_t strid
     if (f_a == f_b) return LBM_EINVAL;
     if (lbm_status st = check_layout(n, stride); st != LBM_OK) return st;
     if (n == 0 || n_steps == 0) return LBM_OK;
-    hipStream_t s = as_stream(stream);
-    switch (p->storage) {
-    case LBM_F64: return dispatch_c16<LBM_F64>(*p, n, stride, codes, tile_records, adj, ns, f_a, f_b, n_steps, s);
-    case LBM_F64_SHIFTED: return dispatch_c16<LBM_F64_SHIFTED>(*p, n, stride, codes, tile_records, adj, ns, f_a, f_b, n_steps, s);
-    case LBM_F32: return dispatch_c16<LBM_F32>(*p, n, stride, codes, tile_records, adj, ns, f_a, f_b, n_steps, s);
-    case LBM_F32_SHIFTED: return dispatch_c16<LBM_F32_SHIFTED>(*p, n, stride, codes, tile_records, adj, ns, f_a, f_b, n_steps, s);
-    case LBM_F16_SHIFTED: return dispatch_c16<LBM_F16_SHIFTED>(*p, n, stride, codes, tile_records, adj, ns, f_a, f_b, n_steps, s);
-    default: return LBM_EINVAL;
+    return step_coded(*p, n, stride, nullptr, codes, tile_records, adj, ns, f_a, f_b, n_steps,
+                      as_stream(stream));
+}
+
+extern "C" lbm_status lbm_narrow_codes(int64_t n, int64_t stride, const int16_t* codes,
+                                       int32_t* tile_records, int8_t* codes8,
+                                       int64_t* n_narrow_tiles, void* workspace,
+                                       size_t* ws_bytes, void* stream) {
+    if (!ws_bytes) return LBM_EINVAL;
+    if (!workspace) {
+        *ws_bytes = 256;
+        return LBM_OK;
     }
+    if (*ws_bytes < 256) return LBM_EWORKSPACE;
+    if (lbm_status st = check_layout(n, stride); st != LBM_OK) return st;
+    if (!codes || !tile_records || !codes8 || !n_narrow_tiles || n <= 0) return LBM_EINVAL;
+    hipStream_t s = as_stream(stream);
+    auto* cnt = static_cast<unsigned long long*>(workspace);
+    k_zero_u64<<<1, 1, 0, s>>>(cnt);
+    if (hipGetLastError() != hipSuccess) return LBM_EHIP;
+    const int64_t tiles = (n + kCTile - 1) / kCTile;
+    k_narrow<<<dim3(unsigned(tiles)), kCTile, 0, s>>>(codes, n, stride, tile_records, codes8, cnt);
+    if (hipGetLastError() != hipSuccess) return LBM_EHIP;
+    unsigned long long t = 0;
+    LBM_TRY_HIP(hipMemcpyAsync(&t, cnt, sizeof(t), hipMemcpyDeviceToHost, s));
+    LBM_TRY_HIP(hipStreamSynchronize(s));
+    *n_narrow_tiles = int64_t(t);
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_step_c8(const lbm_params* p, int64_t n, int64_t stride,
+                                  const int8_t* codes8, const int16_t* codes,
+                                  const int32_t* tile_records, const uint32_t* adj,
+                                  const double* ns, void* f_a, void* f_b, int32_t n_steps,
+                                  void* stream) {
+    if (!valid_params(p) || !codes8 || !codes || !tile_records || !adj || !f_a || !f_b ||
+        n_steps < 0)
+        return LBM_EINVAL;
+    if (f_a == f_b) return LBM_EINVAL;
+    if (lbm_status st = check_layout(n, stride); st != LBM_OK) return st;
+    if (n == 0 || n_steps == 0) return LBM_OK;
+    return step_coded(*p, n, stride, codes8, codes, tile_records, adj, ns, f_a, f_b, n_steps,
+                      as_stream(stream));
 }

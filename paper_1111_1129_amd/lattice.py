@@ -202,12 +202,19 @@ def partition_stats(lat: Lattice, n_chunks: int, n: int | None = None, stream=No
 
 @dataclasses.dataclass
 class Compressed:
-    """16-bit adjacency codes of a lattice (lbm_compress_adjacency)."""
+    """16-bit adjacency codes of a lattice (lbm_compress_adjacency), and
+    their 8-bit form in the tiles that allow it (lbm_narrow_codes)."""
 
     codes: torch.Tensor         # int16 [18][stride]
-    tile_records: torch.Tensor  # int32 [ceil(n / 256)][20]: 18 offsets, escapes, 0
+    tile_records: torch.Tensor  # int32 [ceil(n / 256)][20]: 18 offsets, escapes, narrow flag
     n: int
     n_escapes: int
+    codes8: torch.Tensor | None = None  # int8 [18][stride] after narrow()
+    n_narrow: int = 0                   # narrow tiles
+
+    @property
+    def n_tiles(self) -> int:
+        return (self.n + 255) // 256
 
 
 def compress(lat: Lattice, n: int | None = None, stream=None) -> Compressed:
@@ -222,6 +229,37 @@ def compress(lat: Lattice, n: int | None = None, stream=None) -> Compressed:
     st, esc, _ = N.lbm_compress_adjacency(n, lat.stride, lat.adj, codes, toff, ws, wsn, stream)
     N._check("lbm_compress_adjacency", st)
     return Compressed(codes, toff, n, esc)
+
+
+def narrow(comp: Compressed, stream=None) -> Compressed:
+    """Add the 8-bit codes of the tiles whose codes fit one byte (sets word 19
+    of every tile record); returns comp."""
+    dev = comp.codes.device
+    S = comp.codes.shape[1]
+    codes8 = torch.empty((18, S), dtype=torch.int8, device=dev)
+    st, _, wsn = N.lbm_narrow_codes(comp.n, S, comp.codes, comp.tile_records, codes8, query=True)
+    N._check("lbm_narrow_codes", st)
+    ws = torch.empty(wsn, dtype=torch.uint8, device=dev)
+    st, cnt, _ = N.lbm_narrow_codes(comp.n, S, comp.codes, comp.tile_records, codes8, ws, wsn,
+                                    stream)
+    N._check("lbm_narrow_codes", st)
+    comp.codes8, comp.n_narrow = codes8, cnt
+    return comp
+
+
+def step_c8(state: State, comp: Compressed, n_steps: int = 1, stream=None):
+    """As step(), reading 8-bit codes in narrow tiles and 16-bit codes
+    elsewhere (results bitwise equal)."""
+    lat = state.lattice
+    assert comp.codes8 is not None, "narrow(comp) first"
+    assert comp.n == state.n and comp.codes.shape[1] == lat.stride
+    st = N.lbm_step_c8(state.params, state.n, lat.stride, comp.codes8, comp.codes,
+                       comp.tile_records, lat.adj, state.ns, state.f, state.g, n_steps, stream)
+    N._check("lbm_step_c8", st)
+    if n_steps % 2 == 1:
+        state.f, state.g = state.g, state.f
+    state.steps += n_steps
+    return state
 
 
 def step_c16(state: State, comp: Compressed, n_steps: int = 1, stream=None):

@@ -42,19 +42,22 @@ def candidate_strides(n: int) -> list[int]:
     return sorted(c for c in cands if c >= n)
 
 
-SWEEPS = ("full", "c16", "inplace", "inplace_c16")
+SWEEPS = ("full", "c16", "c8", "inplace", "inplace_c16")
 
 
 class Sweeper:
     """One way of stepping a lattice: the two-array sweep over the full
-    adjacency list ("full") or over 16-bit codes ("c16"), or the in-place
-    sweep on one array over either ("inplace", "inplace_c16").  Results are
+    adjacency list ("full"), over 16-bit codes ("c16") or over 8-bit codes
+    where a tile allows them ("c8"), or the in-place sweep on one array over
+    the full list or 16-bit codes ("inplace", "inplace_c16").  Results are
     bitwise the same after an even number of steps."""
 
     def __init__(self, lat, kind: str = "full"):
         assert kind in SWEEPS, kind
         self.lat, self.kind = lat, kind
-        self.comp = L.compress(lat) if kind.endswith("c16") else None
+        self.comp = L.compress(lat) if kind.endswith(("c16", "c8")) else None
+        if kind == "c8":
+            L.narrow(self.comp)
 
     def init(self, prm, **kw):
         if self.kind.startswith("inplace"):
@@ -66,6 +69,8 @@ class Sweeper:
             return L.step(st, n_steps)
         if self.kind == "c16":
             return L.step_c16(st, self.comp, n_steps)
+        if self.kind == "c8":
+            return L.step_c8(st, self.comp, n_steps)
         return L.step_inplace(st, n_steps, self.comp)
 
 
@@ -129,8 +134,8 @@ def tune_layout(flags: torch.Tensor, periodic: int, order: str = "lex", param: i
 def tune_sweep(flags: torch.Tensor, periodic: int, order: str = "lex", param: int = 0,
                storage: str = "f64", force=(1e-6, 0.0, 0.0), sweeps: int = 6,
                kinds=SWEEPS, candidates: list[int] | None = None):
-    """Pick the sweep kind (full list, 16-bit codes, in place, in place over
-    codes) and its layout: each kind's layout is tuned, and the fastest kind
+    """Pick the sweep kind (full list, 16-bit or 8-bit codes, in place, in
+    place over codes) and its layout: each kind's layout is tuned, and the fastest kind
     wins.  Which one that is depends on the storage form and the ordering
     (codes pay off where tiles are escape-free; in place where the PDF bytes
     dominate).  Returns (kind, Layout, {kind: MFLUPS})."""

@@ -254,3 +254,38 @@ def test_adjoint_c16_argument_errors(lib):
     assert call(n=0) == N.LBM_EINVAL
     assert call(stride=9) == N.LBM_EINVAL
     assert call(stride=(1 << 32) // 19 + 1) == N.LBM_EOVERFLOW
+
+
+def test_c8_argument_errors(lib):
+    from paper_1111_1129_amd import _native as N
+    P = C.c_void_p
+    lib.lbm_step_c8.restype = C.c_int32
+    lib.lbm_step_c8.argtypes = [C.POINTER(N.lbm_params), C.c_int64, C.c_int64, P, P, P, P, P, P,
+                                P, C.c_int32, P]
+    prm = N.make_params(0.8, 3 / 16)
+    d, e = P(4096), P(8192)
+
+    def step(c8=d, c16=d, recs=d, fa=d, fb=e, n=10, stride=10, steps=1):
+        return lib.lbm_step_c8(C.byref(prm), n, stride, c8, c16, recs, d, None, fa, fb, steps,
+                               None)
+
+    assert step(c8=None) == N.LBM_EINVAL
+    assert step(c16=None) == N.LBM_EINVAL
+    assert step(recs=None) == N.LBM_EINVAL
+    assert step(fb=d) == N.LBM_EINVAL                  # in place is not allowed here
+    assert step(steps=-1) == N.LBM_EINVAL
+    assert step(stride=9) == N.LBM_EINVAL
+    assert step(n=0, stride=0) == N.LBM_OK             # nothing to do, no launch
+    lib.lbm_narrow_codes.restype = C.c_int32
+    lib.lbm_narrow_codes.argtypes = [C.c_int64, C.c_int64, P, P, P, C.POINTER(C.c_int64), P,
+                                     C.POINTER(C.c_size_t), P]
+    ws = C.c_size_t(0)
+    cnt = C.c_int64(0)
+    assert lib.lbm_narrow_codes(10, 10, d, d, d, C.byref(cnt), None, C.byref(ws), None) == N.LBM_OK
+    assert ws.value == 256
+    small = C.c_size_t(8)
+    assert lib.lbm_narrow_codes(10, 10, d, d, d, C.byref(cnt), d, C.byref(small),
+                                None) == N.LBM_EWORKSPACE
+    assert lib.lbm_narrow_codes(10, 10, None, d, d, C.byref(cnt), d, C.byref(ws),
+                                None) == N.LBM_EINVAL
+    assert lib.lbm_narrow_codes(0, 0, d, d, d, C.byref(cnt), d, C.byref(ws), None) == N.LBM_EINVAL

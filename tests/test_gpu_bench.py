@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-@pytest.mark.parametrize("sweep", ["c16", "full", "inplace_c16"])
+@pytest.mark.parametrize("sweep", ["c8", "c16", "full", "inplace_c16"])
 def test_bench_json_contract(sweep):
     cmd = [sys.executable, os.path.join(ROOT, "bench.py"), "--workload", "small_packing",
            "--sweep", sweep, "--layout", "aligned", "--steps", "2", "--warmup", "1",
@@ -43,6 +43,6 @@ def test_bench_sweep_auto_picks_a_kind():
     res = subprocess.run(cmd, capture_output=True, text=True, timeout=300)
     assert res.returncode == 0, res.stderr[-2000:]
     d = json.loads(res.stdout.strip().splitlines()[-1])
-    assert d["config"]["sweep"] in ("full", "c16", "inplace", "inplace_c16")
+    assert d["config"]["sweep"] in ("full", "c16", "c8", "inplace", "inplace_c16")
     assert "sweep kinds (MFLUPS)" in res.stderr
     assert d["cpu_baseline"] is None

@@ -41,6 +41,14 @@ def test_sweep_byte_counts():
     assert bench.sweep_bytes("f64", "c16") == pytest.approx(304 + 36 + 80 / 256)
     assert bench.sweep_bytes("f64", "inplace") == pytest.approx(304 + 36)
     assert bench.sweep_bytes("f16s", "inplace_c16") == pytest.approx(76 + (36 + 80 / 256) / 2)
+    # 8-bit codes: by the shares of cells in narrow tiles and in tiles with escapes
+    assert bench.sweep_bytes("f64", "c8", 1.0, 0.0) == pytest.approx(304 + 18 + 80 / 256)
+    assert bench.sweep_bytes("f64", "c8", 0.9, 0.0) == pytest.approx(304 + 0.9 * 18 + 0.1 * 36
+                                                                     + 80 / 256)
+    assert bench.sweep_bytes("f64", "c8", 0.0, 1.0) == pytest.approx(304 + 72 + 80 / 256)
+    assert bench.sweep_bytes("f64", "c16", 0.0, 0.25) == pytest.approx(304 + 0.75 * 36 + 18
+                                                                      + 80 / 256)
+    assert bench.sweep_bytes("f64", "c8") == bench.sweep_bytes("f64", "c16")
     for kind in bench.SWEEP_KERNELS:
         assert bench.sweep_bytes("f64", kind) > bench.sweep_bytes("f32", kind) > \
             bench.sweep_bytes("f16s", kind)
