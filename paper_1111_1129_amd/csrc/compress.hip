@@ -42,8 +42,7 @@ constexpr int kRec = kCodeRec;
 // every thread encodes its entries against the 18 bases.
 __global__ __launch_bounds__(kCTile) void k_compress(const uint32_t* __restrict__ adj, int64_t n,
                                                      int64_t stride, int16_t* __restrict__ codes,
-                                                     int32_t* __restrict__ rec,
-                                                     unsigned long long* __restrict__ escapes) {
+                                                     int32_t* __restrict__ rec) {
     constexpr int kWaves = kCTile / 64;
     __shared__ int32_t lo_s[Q - 1][kCTile], hi_s[Q - 1][kCTile];
     __shared__ int32_t base_s[Q - 1];
@@ -111,11 +110,28 @@ __global__ __launch_bounds__(kCTile) void k_compress(const uint32_t* __restrict_
     if (threadIdx.x == 0) {
         rec[tile * kRec + Q - 1] = int32_t(tile_esc);
         rec[tile * kRec + Q] = 0;
-        if (tile_esc) atomicAdd(escapes, (unsigned long long)tile_esc);
     }
 }
 
-__global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
+// Sum of one word over all tile records, in one workgroup (the per-tile
+// counts are totalled here rather than by a global atomic per tile, which
+// the 8 XCDs would serialise on one address).
+constexpr int kSumBlock = 1024;
+__global__ __launch_bounds__(kSumBlock) void k_sum_records(const int32_t* __restrict__ rec,
+                                                           int64_t tiles, int word,
+                                                           unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long part[kSumBlock / 64];
+    unsigned long long s = 0;
+    for (int64_t t = threadIdx.x; t < tiles; t += kSumBlock) s += uint32_t(rec[t * kRec + word]);
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (threadIdx.x % 64 == 0) part[threadIdx.x / 64] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long total = 0;
+        for (int w = 0; w < kSumBlock / 64; ++w) total += part[w];
+        *out = total;
+    }
+}
 
 constexpr int8_t kNarrowBounce = -128;
 constexpr int32_t kNarrowMax = 127;
@@ -124,8 +140,7 @@ constexpr int32_t kNarrowMax = 127;
 // fit (a tile with escapes never does).  Codes of a wide tile are stored as 0.
 __global__ __launch_bounds__(kCTile) void k_narrow(const int16_t* __restrict__ codes, int64_t n,
                                                    int64_t stride, int32_t* __restrict__ rec,
-                                                   int8_t* __restrict__ codes8,
-                                                   unsigned long long* __restrict__ narrow_tiles) {
+                                                   int8_t* __restrict__ codes8) {
     const int64_t tile = blockIdx.x;
     const int64_t m = tile * kCTile + threadIdx.x;
     const bool live = m < n;
@@ -144,10 +159,7 @@ __global__ __launch_bounds__(kCTile) void k_narrow(const int16_t* __restrict__ c
             codes8[k * stride + m] =
                 narrow ? (cd[k] == kCodeBounce ? kNarrowBounce : int8_t(cd[k])) : int8_t(0);
     }
-    if (threadIdx.x == 0) {
-        rec[tile * kRec + Q] = narrow ? 1 : 0;
-        if (narrow) atomicAdd(narrow_tiles, 1ull);
-    }
+    if (threadIdx.x == 0) rec[tile * kRec + Q] = narrow ? 1 : 0;
 }
 
 // One cell update of an escape-free tile, the slots rebuilt from the 16-bit
@@ -297,10 +309,10 @@ extern "C" lbm_status lbm_compress_adjacency(int64_t n, int64_t stride, const ui
     if (!adj || !codes || !tile_records || !n_escapes || n <= 0) return LBM_EINVAL;
     hipStream_t s = as_stream(stream);
     auto* esc = static_cast<unsigned long long*>(workspace);
-    k_zero_u64<<<1, 1, 0, s>>>(esc);
-    if (hipGetLastError() != hipSuccess) return LBM_EHIP;
     const int64_t tiles = (n + kCTile - 1) / kCTile;
-    k_compress<<<dim3(unsigned(tiles)), kCTile, 0, s>>>(adj, n, stride, codes, tile_records, esc);
+    k_compress<<<dim3(unsigned(tiles)), kCTile, 0, s>>>(adj, n, stride, codes, tile_records);
+    if (hipGetLastError() != hipSuccess) return LBM_EHIP;
+    k_sum_records<<<1, kSumBlock, 0, s>>>(tile_records, tiles, Q - 1, esc);
     if (hipGetLastError() != hipSuccess) return LBM_EHIP;
     unsigned long long e = 0;
     LBM_TRY_HIP(hipMemcpyAsync(&e, esc, sizeof(e), hipMemcpyDeviceToHost, s));
@@ -336,10 +348,10 @@ extern "C" lbm_status lbm_narrow_codes(int64_t n, int64_t stride, const int16_t*
     if (!codes || !tile_records || !codes8 || !n_narrow_tiles || n <= 0) return LBM_EINVAL;
     hipStream_t s = as_stream(stream);
     auto* cnt = static_cast<unsigned long long*>(workspace);
-    k_zero_u64<<<1, 1, 0, s>>>(cnt);
-    if (hipGetLastError() != hipSuccess) return LBM_EHIP;
     const int64_t tiles = (n + kCTile - 1) / kCTile;
-    k_narrow<<<dim3(unsigned(tiles)), kCTile, 0, s>>>(codes, n, stride, tile_records, codes8, cnt);
+    k_narrow<<<dim3(unsigned(tiles)), kCTile, 0, s>>>(codes, n, stride, tile_records, codes8);
+    if (hipGetLastError() != hipSuccess) return LBM_EHIP;
+    k_sum_records<<<1, kSumBlock, 0, s>>>(tile_records, tiles, Q, cnt);
     if (hipGetLastError() != hipSuccess) return LBM_EHIP;
     unsigned long long t = 0;
     LBM_TRY_HIP(hipMemcpyAsync(&t, cnt, sizeof(t), hipMemcpyDeviceToHost, s));
