@@ -14,7 +14,7 @@ The sweep reads the adjacency as 8-bit codes in the tiles whose codes fit a
 byte and as 16-bit codes elsewhere (``--sweep c8``: the codes are built inside
 the step; results are bitwise those of the sweep over the full uint32 list,
 ``--sweep full``); ``c16`` reads 16-bit codes only; ``inplace`` /
-``inplace_c16`` step one PDF array instead of two.
+``inplace_c16`` / ``inplace_c8`` step one PDF array instead of two.
 
 Experiments (``--experiment``, one JSON line per configuration, see
 bench_experiments.py): precision (FP64 / FP32 / shifted FP16 storage on the
@@ -53,7 +53,8 @@ PDF_SIZE = {"f64": 8, "f64s": 8, "f32": 4, "f32s": 4, "f16s": 2}
 SWEEP_KERNELS = {"full": ("k_trt", "trt.hip"), "c16": ("k_trt_c16", "compress.hip"),
                  "c8": ("k_trt_c8", "compress.hip"),
                  "inplace": ("k_gather_scatter + k_local", "inplace.hip"),
-                 "inplace_c16": ("k_gather_scatter + k_local", "inplace.hip")}
+                 "inplace_c16": ("k_gather_scatter + k_local", "inplace.hip"),
+                 "inplace_c8": ("k_gather_scatter + k_local", "inplace.hip")}
 
 
 def sweep_bytes(storage: str, kind: str, narrow: float = 0.0, escape: float = 0.0) -> float:
@@ -104,7 +105,7 @@ def parse():
     ap.add_argument("--sweep", default="c8", choices=list(SWEEP_KERNELS) + ["auto"],
                     help="full: two arrays, uint32 adjacency; c16: two arrays, 16-bit codes; "
                          "c8: two arrays, 8-bit codes where a tile allows them, else 16-bit; "
-                         "inplace / inplace_c16: one PDF array; auto: the fastest kind "
+                         "inplace / inplace_c16 / inplace_c8: one PDF array; auto: the fastest kind "
                          "on this geometry (tuned before the timed region, with --layout tuned)")
     ap.add_argument("--layout", default="tuned", choices=["tuned", "aligned", "given"],
                     help="tuned: time candidate row strides / store policies on the geometry "

@@ -451,7 +451,7 @@ def ordering_tuner(a):
 def bytes_resident(storage, kind):
     """HBM bytes per cell held by the arrays a sweep needs."""
     pdf = 19 * PDF_SIZE[storage] * (1 if kind.startswith("inplace") else 2)
-    return pdf + 72 + (36 if kind.endswith(("c16", "c8")) else 0) + (18 if kind == "c8" else 0)
+    return pdf + 72 + (36 if kind.endswith(("c16", "c8")) else 0) + (18 if kind.endswith("c8") else 0)
 
 
 def compressed(a):
@@ -461,7 +461,7 @@ def compressed(a):
     form and ordering, bitwise equality of the results after the same (even)
     number of sweeps."""
     sweeps = 400
-    kinds = ("full", "c16", "c8", "inplace", "inplace_c16")
+    kinds = ("full", "c16", "c8", "inplace", "inplace_c16", "inplace_c8")
     tube = I.packing_tube(2)
     cases = [("tube_packing", tube, "lex", 0),
              ("tube_packing", tube, "blocked", 16),
@@ -494,7 +494,8 @@ def compressed(a):
                         make = L.init
                     else:
                         def run(k, st):
-                            return L.step_inplace(st, k, comp if kind == "inplace_c16" else None)
+                            return L.step_inplace(st, k, None if kind == "inplace" else comp,
+                                                  c8=kind == "inplace_c8")
                         make = L.init_inplace
                     st = make(lat, prm)
                     run(2, st)

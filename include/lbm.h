@@ -421,6 +421,25 @@ lbm_status lbm_step_inplace(const lbm_params* p, int64_t n, int64_t stride, cons
                             const int16_t* codes, const int32_t* tile_records, const double* ns,
                             void* f, int32_t phase, int32_t n_steps, void* stream);
 
+/*
+ * lbm_step_inplace_c8 -- lbm_step_inplace whose phase-0 steps read the 8-bit
+ * codes of lbm_narrow_codes in narrow tiles, the 16-bit codes in the other
+ * tiles and adj in tiles with escapes (the same byte reduction of the
+ * adjacency read by the Sec. 7 pull updates as lbm_step_c8).  Results are
+ * bitwise those of lbm_step_inplace.
+ *
+ *  codes8, codes, tile_records  from lbm_narrow_codes and
+ *        lbm_compress_adjacency for the same n, stride and adj (all three
+ *        required).
+ *  The other arguments as lbm_step_inplace.
+ * Errors: LBM_EINVAL (bad params, NULL pointers, phase not 0/1),
+ * LBM_EOVERFLOW, LBM_EHIP.
+ */
+lbm_status lbm_step_inplace_c8(const lbm_params* p, int64_t n, int64_t stride,
+                               const uint32_t* adj, const int8_t* codes8, const int16_t* codes,
+                               const int32_t* tile_records, const double* ns, void* f,
+                               int32_t phase, int32_t n_steps, void* stream);
+
 /* Library version (major*10000 + minor*100 + patch) and a static string for a
  * status code.  Both are host-only and allocate nothing. */
 int32_t lbm_version(void);

@@ -28,7 +28,7 @@ FLAG_XCD_CHUNK_SHIFT = 8
 ENTRY_POINTS = ("lbm_build_adjacency", "lbm_init", "lbm_step", "lbm_step_adjoint",
                 "lbm_moments", "lbm_partition_stats", "lbm_compress_adjacency", "lbm_step_c16",
                 "lbm_step_inplace", "lbm_step_adjoint_c16", "lbm_narrow_codes", "lbm_step_c8",
-                "lbm_version", "lbm_status_string")
+                "lbm_step_inplace_c8", "lbm_version", "lbm_status_string")
 
 
 class lbm_geom(C.Structure):
@@ -99,6 +99,9 @@ def load(path: str = LIB_PATH):
                                          C.POINTER(SZ), P]
         lib.lbm_step_c8.restype = I32
         lib.lbm_step_c8.argtypes = [C.POINTER(lbm_params), I64, I64, P, P, P, P, P, P, P, I32, P]
+        lib.lbm_step_inplace_c8.restype = I32
+        lib.lbm_step_inplace_c8.argtypes = [C.POINTER(lbm_params), I64, I64, P, P, P, P, P, P,
+                                            I32, I32, P]
         lib.lbm_version.restype = I32
         lib.lbm_version.argtypes = []
         lib.lbm_status_string.restype = C.c_char_p
@@ -260,6 +263,13 @@ def lbm_step_adjoint_c16(params: lbm_params, n, stride, codes, tile_records, adj
                                        _ptr(tile_records), _ptr(adj), _ptr(f_t), _ptr(ns),
                                        _ptr(lam_next), _ptr(lam_t), _ptr(grad_ns),
                                        _stream(stream))
+
+
+def lbm_step_inplace_c8(params: lbm_params, n, stride, adj, codes8, codes, tile_records, ns, f,
+                        phase, n_steps, stream=None):
+    return load().lbm_step_inplace_c8(C.byref(params), n, stride, _ptr(adj), _ptr(codes8),
+                                      _ptr(codes), _ptr(tile_records), _ptr(ns), _ptr(f),
+                                      int(phase), int(n_steps), _stream(stream))
 
 
 def lbm_version() -> int:

@@ -19,9 +19,11 @@
 // synchronisation than the launch boundary.  The collision sees exactly the
 // values the two-array sweep sees, so after an even number of steps the
 // array is bitwise the two-array result; the gather-scatter step can read
-// the 16-bit codes of lbm_compress_adjacency instead of adj.
+// the 16-bit codes of lbm_compress_adjacency instead of adj, and the 8-bit
+// codes of lbm_narrow_codes in the tiles that have them.
 // Per two steps a cell moves 2 x 19 x 2 PDFs and the adjacency once: 340
-// bytes per FP64 update on average (322 with 16-bit codes) instead of 376.
+// bytes per FP64 update on average (322 with 16-bit codes, 313 with 8-bit
+// codes in every tile) instead of 376.
 #include <algorithm>
 
 #include "lbm_device.hpp"
@@ -29,45 +31,63 @@
 
 namespace lbm {
 
-constexpr int kIBlock = kCodeTile;  // a workgroup is one tile of the 16-bit codes
+constexpr int kIBlock = kCodeTile;  // a workgroup is one tile of the codes
 
-// Slots of the gather-scatter step for one cell: s[k] = adj(k + 1, m).
-template <bool C16>
-__device__ __forceinline__ void gather_slots(uint32_t* s, const uint32_t* __restrict__ adj,
-                                             const int16_t* __restrict__ codes,
-                                             const int32_t* __restrict__ rec, int64_t m,
-                                             int64_t stride) {
-    if constexpr (!C16) {
-        const uint32_t* ap = adj + m;
+// Where the gather-scatter step finds a cell's slots.
+enum SlotSource { kFromAdj = 0, kFrom16 = 1, kFrom8 = 2 };
+constexpr int32_t kBounce8 = -128;  // bounce-back in the 8-bit codes
+
+// Slots rebuilt from the 16-bit (SRC = kFrom16) or 8-bit (kFrom8) codes of
+// the cell's tile: s[k] = adj(k + 1, m).
+template <int SRC, class CT>
+__device__ __forceinline__ void slots_from_codes(uint32_t* s, const CT* __restrict__ codes,
+                                                 const int32_t* __restrict__ rec, int64_t m,
+                                                 int64_t stride) {
+    constexpr int32_t bounce = SRC == kFrom8 ? kBounce8 : int32_t(kCodeBounce);
+    const CT* cp = codes + m;
+    int32_t cd[Q - 1];
 #pragma unroll
-        for (int k = 0; k < Q - 1; ++k) s[k] = ld_stream(ap + k * stride);
-    } else {
-        const int16_t* cp = codes + m;
-        int32_t cd[Q - 1];
+    for (int k = 0; k < Q - 1; ++k) cd[k] = ld_stream(cp + k * stride);
+    const uint32_t S = uint32_t(stride), mm = uint32_t(m);
 #pragma unroll
-        for (int k = 0; k < Q - 1; ++k) cd[k] = ld_stream(cp + k * stride);
-        const uint32_t S = uint32_t(stride), mm = uint32_t(m);
-#pragma unroll
-        for (int k = 0; k < Q - 1; ++k) {
-            const uint32_t i = k + 1;
-            const uint32_t streamed = i * S + uint32_t(rec[k]) + mm + uint32_t(cd[k]);
-            const uint32_t bounced = uint32_t(opp(int(i))) * S + mm;
-            s[k] = cd[k] == kCodeBounce ? bounced : streamed;
-        }
+    for (int k = 0; k < Q - 1; ++k) {
+        const uint32_t i = k + 1;
+        const uint32_t streamed = i * S + uint32_t(rec[k]) + mm + uint32_t(cd[k]);
+        const uint32_t bounced = uint32_t(opp(int(i))) * S + mm;
+        s[k] = cd[k] == bounce ? bounced : streamed;
     }
 }
 
-template <int ST, bool PBB, bool NT, bool C16>
+// Slots of the gather-scatter step for one cell: s[k] = adj(k + 1, m).
+template <int SRC>
+__device__ __forceinline__ void gather_slots(uint32_t* s, const uint32_t* __restrict__ adj,
+                                             const int16_t* __restrict__ codes,
+                                             const int8_t* __restrict__ codes8,
+                                             const int32_t* __restrict__ rec, int64_t m,
+                                             int64_t stride) {
+    if constexpr (SRC == kFromAdj) {
+        const uint32_t* ap = adj + m;
+#pragma unroll
+        for (int k = 0; k < Q - 1; ++k) s[k] = ld_stream(ap + k * stride);
+    } else if constexpr (SRC == kFrom16) {
+        slots_from_codes<kFrom16>(s, codes, rec, m, stride);
+    } else {
+        slots_from_codes<kFrom8>(s, codes8, rec, m, stride);
+    }
+}
+
+template <int ST, bool PBB, bool NT, int SRC>
 __device__ __forceinline__ void gather_scatter_cell(typename Storage<ST>::T* f,
                                                     const uint32_t* __restrict__ adj,
                                                     const int16_t* __restrict__ codes,
+                                                    const int8_t* __restrict__ codes8,
                                                     const int32_t* __restrict__ rec,
                                                     const double* __restrict__ ns, int64_t m,
                                                     int64_t stride, const TrtConst& c) {
     using T = typename Storage<ST>::T;
     using A = typename Storage<ST>::A;
     uint32_t s[Q - 1];
-    gather_slots<C16>(s, adj, codes, rec, m, stride);
+    gather_slots<SRC>(s, adj, codes, codes8, rec, m, stride);
     A g[Q];
     g[0] = ld<T, A>(f + m);
 #pragma unroll
@@ -82,10 +102,14 @@ __device__ __forceinline__ void gather_scatter_cell(typename Storage<ST>::T* f,
     for (int k = 0; k < Q - 1; ++k) st<T, A, NT>(f + s[k], out[opp(k + 1)]);
 }
 
-template <int ST, bool PBB, bool NT, bool C16>
+// SRC: the narrowest code form the launch may use; each tile then takes what
+// its record allows (a workgroup-uniform choice): 8-bit codes in a narrow
+// tile (kFrom8 only), the full list in a tile with escapes, else 16-bit codes.
+template <int ST, bool PBB, bool NT, int SRC>
 __global__ __launch_bounds__(kIBlock) void k_gather_scatter(typename Storage<ST>::T* f,
                                                             const uint32_t* __restrict__ adj,
                                                             const int16_t* __restrict__ codes,
+                                                            const int8_t* __restrict__ codes8,
                                                             const int32_t* __restrict__ tile_rec,
                                                             const double* __restrict__ ns,
                                                             int64_t n, int64_t stride, TrtConst c,
@@ -93,14 +117,16 @@ __global__ __launch_bounds__(kIBlock) void k_gather_scatter(typename Storage<ST>
     const int64_t tile = logical_block(chunk_shift);
     const int64_t m = tile * kIBlock + threadIdx.x;
     if (m >= n) return;
-    if constexpr (C16) {
-        const int32_t* rec = tile_rec + tile * kCodeRec;  // uniform over the workgroup
-        if (rec[Q - 1] != 0)  // the tile has escape codes: use the full list
-            gather_scatter_cell<ST, PBB, NT, false>(f, adj, codes, rec, ns, m, stride, c);
-        else
-            gather_scatter_cell<ST, PBB, NT, true>(f, adj, codes, rec, ns, m, stride, c);
+    if constexpr (SRC == kFromAdj) {
+        gather_scatter_cell<ST, PBB, NT, kFromAdj>(f, adj, codes, codes8, nullptr, ns, m, stride, c);
     } else {
-        gather_scatter_cell<ST, PBB, NT, false>(f, adj, codes, nullptr, ns, m, stride, c);
+        const int32_t* rec = tile_rec + tile * kCodeRec;  // uniform over the workgroup
+        if (SRC == kFrom8 && rec[Q] != 0)
+            gather_scatter_cell<ST, PBB, NT, kFrom8>(f, adj, codes, codes8, rec, ns, m, stride, c);
+        else if (rec[Q - 1] != 0)  // the tile has escape codes: use the full list
+            gather_scatter_cell<ST, PBB, NT, kFromAdj>(f, adj, codes, codes8, rec, ns, m, stride, c);
+        else
+            gather_scatter_cell<ST, PBB, NT, kFrom16>(f, adj, codes, codes8, rec, ns, m, stride, c);
     }
 }
 
@@ -127,18 +153,21 @@ __global__ __launch_bounds__(kIBlock) void k_local(typename Storage<ST>::T* f,
 
 template <int ST, bool PBB, bool NT>
 lbm_status launch_inplace(const TrtConst& c, int cs, int64_t n, int64_t stride,
-                          const uint32_t* adj, const int16_t* codes, const int32_t* rec,
-                          const double* ns, void* fv, int phase, int n_steps, hipStream_t s) {
+                          const uint32_t* adj, const int16_t* codes, const int8_t* codes8,
+                          const int32_t* rec, const double* ns, void* fv, int phase, int n_steps,
+                          hipStream_t s) {
     using T = typename Storage<ST>::T;
     T* f = static_cast<T*>(fv);
     const int64_t grid = grid_blocks(n, kIBlock, cs);
     const dim3 g{unsigned(grid)}, b{unsigned(kIBlock)};
     for (int k = 0; k < n_steps; ++k) {
         if (((phase + k) & 1) == 0) {
-            if (codes)
-                k_gather_scatter<ST, PBB, NT, true><<<g, b, 0, s>>>(f, adj, codes, rec, ns, n, stride, c, cs);
+            if (codes8)
+                k_gather_scatter<ST, PBB, NT, kFrom8><<<g, b, 0, s>>>(f, adj, codes, codes8, rec, ns, n, stride, c, cs);
+            else if (codes)
+                k_gather_scatter<ST, PBB, NT, kFrom16><<<g, b, 0, s>>>(f, adj, codes, codes8, rec, ns, n, stride, c, cs);
             else
-                k_gather_scatter<ST, PBB, NT, false><<<g, b, 0, s>>>(f, adj, codes, rec, ns, n, stride, c, cs);
+                k_gather_scatter<ST, PBB, NT, kFromAdj><<<g, b, 0, s>>>(f, adj, codes, codes8, rec, ns, n, stride, c, cs);
         } else {
             k_local<ST, PBB, NT><<<g, b, 0, s>>>(f, ns, n, stride, c, cs);
         }
@@ -149,16 +178,29 @@ lbm_status launch_inplace(const TrtConst& c, int cs, int64_t n, int64_t stride,
 
 template <int ST>
 lbm_status dispatch_inplace(const lbm_params& p, int64_t n, int64_t stride, const uint32_t* adj,
-                            const int16_t* codes, const int32_t* rec, const double* ns, void* f,
-                            int phase, int n_steps, hipStream_t s) {
+                            const int16_t* codes, const int8_t* codes8, const int32_t* rec,
+                            const double* ns, void* f, int phase, int n_steps, hipStream_t s) {
     const TrtConst c = make_trt_const(p);
     const int cs = chunk_shift_for(p.flags, n, kIBlock);
     const bool nt = p.flags & LBM_FLAG_NONTEMPORAL;
     if (ns)
-        return nt ? launch_inplace<ST, true, true>(c, cs, n, stride, adj, codes, rec, ns, f, phase, n_steps, s)
-                  : launch_inplace<ST, true, false>(c, cs, n, stride, adj, codes, rec, ns, f, phase, n_steps, s);
-    return nt ? launch_inplace<ST, false, true>(c, cs, n, stride, adj, codes, rec, ns, f, phase, n_steps, s)
-              : launch_inplace<ST, false, false>(c, cs, n, stride, adj, codes, rec, ns, f, phase, n_steps, s);
+        return nt ? launch_inplace<ST, true, true>(c, cs, n, stride, adj, codes, codes8, rec, ns, f, phase, n_steps, s)
+                  : launch_inplace<ST, true, false>(c, cs, n, stride, adj, codes, codes8, rec, ns, f, phase, n_steps, s);
+    return nt ? launch_inplace<ST, false, true>(c, cs, n, stride, adj, codes, codes8, rec, ns, f, phase, n_steps, s)
+              : launch_inplace<ST, false, false>(c, cs, n, stride, adj, codes, codes8, rec, ns, f, phase, n_steps, s);
+}
+
+lbm_status step_inplace(const lbm_params& p, int64_t n, int64_t stride, const uint32_t* adj,
+                        const int16_t* codes, const int8_t* codes8, const int32_t* rec,
+                        const double* ns, void* f, int phase, int n_steps, hipStream_t s) {
+    switch (p.storage) {
+    case LBM_F64: return dispatch_inplace<LBM_F64>(p, n, stride, adj, codes, codes8, rec, ns, f, phase, n_steps, s);
+    case LBM_F64_SHIFTED: return dispatch_inplace<LBM_F64_SHIFTED>(p, n, stride, adj, codes, codes8, rec, ns, f, phase, n_steps, s);
+    case LBM_F32: return dispatch_inplace<LBM_F32>(p, n, stride, adj, codes, codes8, rec, ns, f, phase, n_steps, s);
+    case LBM_F32_SHIFTED: return dispatch_inplace<LBM_F32_SHIFTED>(p, n, stride, adj, codes, codes8, rec, ns, f, phase, n_steps, s);
+    case LBM_F16_SHIFTED: return dispatch_inplace<LBM_F16_SHIFTED>(p, n, stride, adj, codes, codes8, rec, ns, f, phase, n_steps, s);
+    default: return LBM_EINVAL;
+    }
 }
 
 }  // namespace lbm
@@ -174,13 +216,20 @@ extern "C" lbm_status lbm_step_inplace(const lbm_params* p, int64_t n, int64_t s
     if ((codes == nullptr) != (tile_records == nullptr)) return LBM_EINVAL;
     if (lbm_status st = check_layout(n, stride); st != LBM_OK) return st;
     if (n == 0 || n_steps == 0) return LBM_OK;
-    hipStream_t s = as_stream(stream);
-    switch (p->storage) {
-    case LBM_F64: return dispatch_inplace<LBM_F64>(*p, n, stride, adj, codes, tile_records, ns, f, phase, n_steps, s);
-    case LBM_F64_SHIFTED: return dispatch_inplace<LBM_F64_SHIFTED>(*p, n, stride, adj, codes, tile_records, ns, f, phase, n_steps, s);
-    case LBM_F32: return dispatch_inplace<LBM_F32>(*p, n, stride, adj, codes, tile_records, ns, f, phase, n_steps, s);
-    case LBM_F32_SHIFTED: return dispatch_inplace<LBM_F32_SHIFTED>(*p, n, stride, adj, codes, tile_records, ns, f, phase, n_steps, s);
-    case LBM_F16_SHIFTED: return dispatch_inplace<LBM_F16_SHIFTED>(*p, n, stride, adj, codes, tile_records, ns, f, phase, n_steps, s);
-    default: return LBM_EINVAL;
-    }
+    return step_inplace(*p, n, stride, adj, codes, nullptr, tile_records, ns, f, phase, n_steps,
+                        as_stream(stream));
+}
+
+extern "C" lbm_status lbm_step_inplace_c8(const lbm_params* p, int64_t n, int64_t stride,
+                                          const uint32_t* adj, const int8_t* codes8,
+                                          const int16_t* codes, const int32_t* tile_records,
+                                          const double* ns, void* f, int32_t phase,
+                                          int32_t n_steps, void* stream) {
+    if (!valid_params(p) || !adj || !codes8 || !codes || !tile_records || !f || n_steps < 0 ||
+        (phase != 0 && phase != 1))
+        return LBM_EINVAL;
+    if (lbm_status st = check_layout(n, stride); st != LBM_OK) return st;
+    if (n == 0 || n_steps == 0) return LBM_OK;
+    return step_inplace(*p, n, stride, adj, codes, codes8, tile_records, ns, f, phase, n_steps,
+                        as_stream(stream));
 }

@@ -304,15 +304,24 @@ def init_inplace(lat: Lattice, prm: N.lbm_params, rho0: float = 1.0, u0=None,
 
 
 def step_inplace(state: InplaceState, n_steps: int = 1, comp: Compressed | None = None,
-                 stream=None) -> InplaceState:
+                 stream=None, c8: bool = False) -> InplaceState:
+    """n_steps in-place sweeps; with comp the gather-scatter steps read the
+    16-bit codes, with c8 also the 8-bit codes of narrow tiles (results
+    bitwise the same)."""
     lat = state.lattice
     codes = recs = None
     if comp is not None:
         assert comp.n == state.n and comp.codes.shape[1] == lat.stride
         codes, recs = comp.codes, comp.tile_records
-    st = N.lbm_step_inplace(state.params, state.n, lat.stride, lat.adj, codes, recs, state.ns,
-                            state.f, state.phase, n_steps, stream)
-    N._check("lbm_step_inplace", st)
+    if c8:
+        assert comp is not None and comp.codes8 is not None, "narrow(comp) first"
+        st = N.lbm_step_inplace_c8(state.params, state.n, lat.stride, lat.adj, comp.codes8, codes,
+                                   recs, state.ns, state.f, state.phase, n_steps, stream)
+        N._check("lbm_step_inplace_c8", st)
+    else:
+        st = N.lbm_step_inplace(state.params, state.n, lat.stride, lat.adj, codes, recs,
+                                state.ns, state.f, state.phase, n_steps, stream)
+        N._check("lbm_step_inplace", st)
     state.phase = (state.phase + n_steps) % 2
     state.steps += n_steps
     return state

@@ -42,21 +42,21 @@ def candidate_strides(n: int) -> list[int]:
     return sorted(c for c in cands if c >= n)
 
 
-SWEEPS = ("full", "c16", "c8", "inplace", "inplace_c16")
+SWEEPS = ("full", "c16", "c8", "inplace", "inplace_c16", "inplace_c8")
 
 
 class Sweeper:
     """One way of stepping a lattice: the two-array sweep over the full
     adjacency list ("full"), over 16-bit codes ("c16") or over 8-bit codes
     where a tile allows them ("c8"), or the in-place sweep on one array over
-    the full list or 16-bit codes ("inplace", "inplace_c16").  Results are
-    bitwise the same after an even number of steps."""
+    the full list or the codes ("inplace", "inplace_c16", "inplace_c8").
+    Results are bitwise the same after an even number of steps."""
 
     def __init__(self, lat, kind: str = "full"):
         assert kind in SWEEPS, kind
         self.lat, self.kind = lat, kind
         self.comp = L.compress(lat) if kind.endswith(("c16", "c8")) else None
-        if kind == "c8":
+        if kind.endswith("c8"):
             L.narrow(self.comp)
 
     def init(self, prm, **kw):
@@ -71,7 +71,7 @@ class Sweeper:
             return L.step_c16(st, self.comp, n_steps)
         if self.kind == "c8":
             return L.step_c8(st, self.comp, n_steps)
-        return L.step_inplace(st, n_steps, self.comp)
+        return L.step_inplace(st, n_steps, self.comp, c8=self.kind.endswith("c8"))
 
 
 def _time_sweeps(lat, prm, sweeps, stream, sweeper=None):

@@ -289,3 +289,22 @@ def test_c8_argument_errors(lib):
     assert lib.lbm_narrow_codes(10, 10, None, d, d, C.byref(cnt), d, C.byref(ws),
                                 None) == N.LBM_EINVAL
     assert lib.lbm_narrow_codes(0, 0, d, d, d, C.byref(cnt), d, C.byref(ws), None) == N.LBM_EINVAL
+
+
+def test_inplace_c8_argument_errors(lib):
+    from paper_1111_1129_amd import _native as N
+    P = C.c_void_p
+    lib.lbm_step_inplace_c8.restype = C.c_int32
+    lib.lbm_step_inplace_c8.argtypes = [C.POINTER(N.lbm_params), C.c_int64, C.c_int64, P, P, P,
+                                        P, P, P, C.c_int32, C.c_int32, P]
+    prm = N.make_params(0.8, 3 / 16)
+    d = P(4096)
+
+    def step(adj=d, c8=d, c16=d, recs=d, f=d, phase=0, steps=1, n=10, stride=10):
+        return lib.lbm_step_inplace_c8(C.byref(prm), n, stride, adj, c8, c16, recs, None, f,
+                                       phase, steps, None)
+
+    for kw in ({"adj": None}, {"c8": None}, {"c16": None}, {"recs": None}, {"f": None},
+               {"phase": 2}, {"steps": -1}, {"stride": 9}):
+        assert step(**kw) == N.LBM_EINVAL, kw
+    assert step(steps=0) == N.LBM_OK  # nothing to do, no launch

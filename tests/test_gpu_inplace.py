@@ -22,26 +22,31 @@ def two_array(lat, prm, f0, steps, ns=None):
     return st.f[:, :lat.n_fluid]
 
 
-def one_array(lat, prm, f0, steps, ns=None, comp=None, split=None):
+def one_array(lat, prm, f0, steps, ns=None, comp=None, split=None, c8=False):
     st = L.init_inplace(lat, prm, ns=ns)
     if f0 is not None:
         st.f.copy_(f0)
     for k in (split or [steps]):
-        L.step_inplace(st, k, comp)
+        L.step_inplace(st, k, comp, c8=c8)
     assert st.phase == steps % 2
     return st
 
 
 @pytest.mark.parametrize("storage", ["f64", "f64s", "f32", "f32s", "f16s"])
-@pytest.mark.parametrize("codes", [False, True])
+@pytest.mark.parametrize("codes", ["adj", "c16", "c8"])
 def test_even_steps_bitwise_equal_two_array(storage, codes):
-    g = I.packing_small(1)
-    print_case("inplace", storage, "codes" if codes else "adj")
-    lat = L.build(dev_flags(g), g.periodic, "lex", 0)
-    comp = L.compress(lat) if codes else None
+    """Lexicographic order of a fully periodic box: narrow, 16-bit and escape
+    tiles in one list."""
+    g = I.random_flags(11, 64, 64, 48, 0.7)
+    print_case("inplace", storage, codes, "random_flags 64x64x48 periodic xyz")
+    lat = L.build(dev_flags(g), 7, "lex", 0)
+    comp = None if codes == "adj" else L.compress(lat)
+    if codes == "c8":
+        L.narrow(comp)
+        assert 0 < comp.n_narrow < comp.n_tiles and comp.n_escapes > 0
     prm = L.params(0.8, 3 / 16, (1e-5, 2e-6, 0), storage)
     ref = two_array(lat, prm, None, 10)
-    st = one_array(lat, prm, None, 10, comp=comp)
+    st = one_array(lat, prm, None, 10, comp=comp, c8=codes == "c8")
     assert torch.equal(st.f[:, :lat.n_fluid], ref)
 
 
@@ -81,16 +86,40 @@ def test_vs_oracle_with_pbb_and_escapes():
 
 
 @pytest.mark.parametrize("n_target", [1, 255, 257])
-def test_tiny_lists(n_target):
+@pytest.mark.parametrize("c8", [False, True])
+def test_tiny_lists(n_target, c8):
     flags = np.zeros((8, 8, 8), dtype=np.uint8)
     flags.ravel()[:n_target] = 1
-    print_case("inplace", "tiny", n_target)
+    print_case("inplace", "tiny", n_target, "c8" if c8 else "c16")
     lat = L.build(torch.from_numpy(flags).cuda(), 7, "lex", 0)
     prm = L.params(0.8, 3 / 16, (1e-4, 0, 0), "f64")
     f0 = torch.from_numpy(random_state(lat.n_fluid, 4, stride=lat.stride)).cuda()
     ref = two_array(lat, prm, f0, 4)
-    st = one_array(lat, prm, f0, 4, comp=L.compress(lat))
+    comp = L.compress(lat)
+    if c8:
+        L.narrow(comp)
+    st = one_array(lat, prm, f0, 4, comp=comp, c8=c8)
     assert torch.equal(st.f[:, :lat.n_fluid], ref)
+
+
+def test_c8_vs_oracle_with_pbb():
+    """In place over 8-bit codes (with 16-bit and escape tiles in the list)
+    against the oracle, partial bounce-back on."""
+    g = I.random_flags(12, 64, 64, 48, 0.7)
+    print_case("inplace", "oracle c8", "random_flags 64x64x48 periodic xyz, pbb")
+    lat = L.build(dev_flags(g), 7, "lex", 0)
+    sp = O.build(g.flags, 7, "lex", 0, stride=lat.stride)
+    n = sp.n_fluid
+    comp = L.narrow(L.compress(lat))
+    assert 0 < comp.n_narrow < comp.n_tiles and comp.n_escapes > 0
+    ns_h = np.zeros(lat.stride)
+    ns_h[:n] = np.random.default_rng(18).uniform(0, 1, n)
+    ns = torch.from_numpy(ns_h).cuda()
+    prm = L.params(0.8, 3 / 16, (1e-5, 0, 0), "f64s")
+    f0 = random_state(n, 19, amp=1e-3, shifted=True, stride=lat.stride)
+    st = one_array(lat, prm, torch.from_numpy(f0).cuda(), 24, ns=ns, comp=comp, c8=True)
+    orc = O.run(oracle_params(prm), sp.adj, f0, 24, ns=ns_h, n0=0, n1=n)
+    assert rel_err_f64(st.f.cpu().numpy()[:, :n], orc[:, :n], shifted=True) <= 1e-12
 
 
 def test_batch_of_geometries():
@@ -119,6 +148,11 @@ def test_full_size_tube():
     assert torch.equal(st.f[:, :lat.n_fluid], ref)
     _, _, tot = L.moments(st, fields=False)
     assert abs(float(tot[0, 0]) / lat.n_fluid - 1.0) < 1e-12  # mass is conserved
+    del st
+    L.narrow(comp)
+    st = one_array(lat, prm, None, 20, comp=comp, c8=True)
+    torch.cuda.synchronize()
+    assert torch.equal(st.f[:, :lat.n_fluid], ref)
 
 
 def test_sweeper_kinds_and_tuner():
