@@ -17,7 +17,7 @@ from paper_1111_1129_amd import _native as N
 from paper_1111_1129_amd import adjoint as AD
 from paper_1111_1129_amd import inputs as I
 from paper_1111_1129_amd import lattice as L
-from paper_1111_1129_amd.tune import tune_layout, tune_ordering, candidate_strides
+from paper_1111_1129_amd.tune import Sweeper, tune_layout, tune_ordering, candidate_strides
 
 from bench import PDF_SIZE, code_mix, sweep_bytes  # one definition of the per-update byte counts
 
@@ -60,6 +60,7 @@ def precision(a):
     sweeps = 500
     forms = ["f64", "f64s", "f32", "f32s", "f16s"]
     layouts = {st: tune_layout(flags, g.periodic, "lex", 0, st, sweeps=4) for st in forms}
+    t_ref_codes = {}
     for gx in (1e-6, 1e-5, 1e-4):
         ref = None
         t_ref = None
@@ -82,19 +83,21 @@ def precision(a):
                    "stride": lat.stride, "nt": lay.nontemporal, "chunk": lay.xcd_chunk,
                    "mass": float(tot[0, 0]), "mean_ux": float(tot[0, 1]) / n}
             if gx == 1e-6:
-                # the same sweep over 16-bit adjacency codes (bitwise the same state)
-                comp = L.compress(lat)
-                sc = L.init(lat, prm)
-                L.step_c16(sc, comp, 2)
-                sc = L.init(lat, prm)
-                tc, _ = timed(lambda: L.step_c16(sc, comp, sweeps))
-                rec["mflups_c16"] = round(n * sweeps / tc / 1e6, 1)
-                rec["c16_equal"] = bool(torch.equal(sc.f[:, :n], state.f[:, :n]))
-                if st == "f64":
-                    t_ref_c16 = tc
-                else:
-                    rec["speedup_c16_vs_f64_c16"] = round(t_ref_c16 / tc, 3)
-                del sc, comp
+                # the same sweeps over the adjacency codes, two arrays and in
+                # place (bitwise the same state after the even sweep count)
+                for kind in ("c16", "c8", "inplace_c8"):
+                    sw = Sweeper(lat, kind)
+                    sc = sw.init(prm)
+                    sw.step(sc, 2)
+                    sc = sw.init(prm)
+                    tc, _ = timed(lambda: sw.step(sc, sweeps))
+                    rec[f"mflups_{kind}"] = round(n * sweeps / tc / 1e6, 1)
+                    rec[f"{kind}_equal"] = bool(torch.equal(sc.f[:, :n], state.f[:, :n]))
+                    if st == "f64":
+                        t_ref_codes[kind] = tc
+                    else:
+                        rec[f"speedup_{kind}_vs_f64_{kind}"] = round(t_ref_codes[kind] / tc, 3)
+                    del sc, sw
             if st == "f64":
                 ref, t_ref = u.clone(), t
             else:
@@ -321,6 +324,14 @@ def batched(a):
         t_c16, _ = timed(lambda: L.step_c16(stc, comp, steps))
         same_c16 = bool(torch.equal(stc.f[:, :tot_n], f_step))
         del stc
+        # and over 8-bit codes where a tile allows them
+        L.narrow(comp)
+        stc = batch.init(prm)
+        L.step_c8(stc, comp, 2)
+        stc = batch.init(prm)
+        t_c8, _ = timed(lambda: L.step_c8(stc, comp, steps))
+        same_c8 = bool(torch.equal(stc.f[:, :tot_n], f_step))
+        del stc
         solos = []
         for fl, g in zip(flags, geoms):
             lat = L.build(fl, g.periodic, "lex")
@@ -358,6 +369,9 @@ def batched(a):
               "mflups_separate_launches": round(tot_n * steps / t_sep / 1e6, 1),
               "mflups_c16_per_step": round(tot_n * steps / t_c16 / 1e6, 1),
               "c16_escapes": comp.n_escapes, "c16_equals_per_step": same_c16,
+              "mflups_c8_per_step": round(tot_n * steps / t_c8 / 1e6, 1),
+              "c8_narrow_tiles": comp.n_narrow, "tiles": comp.n_tiles,
+              "c8_equals_per_step": same_c8,
               "persistent_equals_per_step": same,
               "gbs_persistent": round(BYTES[storage] * tot_n * steps / t_pers / 1e9, 1),
               "gbs_launch_per_step": round(BYTES[storage] * tot_n * steps / t_step / 1e9, 1),
