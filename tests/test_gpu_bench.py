@@ -43,6 +43,7 @@ def test_bench_sweep_auto_picks_a_kind():
     res = subprocess.run(cmd, capture_output=True, text=True, timeout=300)
     assert res.returncode == 0, res.stderr[-2000:]
     d = json.loads(res.stdout.strip().splitlines()[-1])
-    assert d["config"]["sweep"] in ("full", "c16", "c8", "inplace", "inplace_c16")
+    from paper_1111_1129_amd.tune import SWEEPS
+    assert d["config"]["sweep"] in SWEEPS
     assert "sweep kinds (MFLUPS)" in res.stderr
     assert d["cpu_baseline"] is None
