@@ -319,8 +319,9 @@ lbm_status lbm_partition_stats(int64_t n, int64_t stride, const uint32_t* adj, i
  *  codes         int16  [18][stride] (output; columns >= n untouched).
  *  tile_records  int32  [ceil(n / 256) * 20] (output).
  *  n_escapes     (host) number of escape codes written.
- *  workspace, ws_bytes  256 bytes of device scratch (query with workspace
- *        NULL).  The call synchronizes the stream to return n_escapes.
+ *  workspace, ws_bytes  2056 bytes of device scratch for partial sums
+ *        (query with workspace NULL).  The call synchronizes the stream to
+ *        return n_escapes.
  * Errors: LBM_EINVAL (NULL pointers, n <= 0), LBM_EOVERFLOW, LBM_EWORKSPACE,
  * LBM_EHIP.
  */
@@ -364,8 +365,9 @@ lbm_status lbm_step_c16(const lbm_params* p, int64_t n, int64_t stride, const in
  *        every record is written).
  *  codes8        int8  [18][stride] (output; columns >= n untouched).
  *  n_narrow_tiles (host) number of narrow tiles.
- *  workspace, ws_bytes  256 bytes of device scratch (query with workspace
- *        NULL).  The call synchronizes the stream to return n_narrow_tiles.
+ *  workspace, ws_bytes  2056 bytes of device scratch for partial sums
+ *        (query with workspace NULL).  The call synchronizes the stream to
+ *        return n_narrow_tiles.
  * Errors: LBM_EINVAL (NULL pointers, n <= 0), LBM_EOVERFLOW, LBM_EWORKSPACE,
  * LBM_EHIP.
  */

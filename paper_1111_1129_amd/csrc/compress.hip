@@ -113,24 +113,50 @@ __global__ __launch_bounds__(kCTile) void k_compress(const uint32_t* __restrict_
     }
 }
 
-// Sum of one word over all tile records, in one workgroup (the per-tile
-// counts are totalled here rather than by a global atomic per tile, which
-// the 8 XCDs would serialise on one address).
-constexpr int kSumBlock = 1024;
+// Sum of one word over all tile records in two passes: up to kSumParts
+// workgroups each total a strided share of the tiles, then one workgroup adds
+// the partial sums (the per-tile counts are totalled here rather than by a
+// global atomic per tile, which the 8 XCDs would serialise on one address).
+constexpr int kSumBlock = 256;
+constexpr int kSumParts = 256;
+constexpr size_t kSumWorkspace = (kSumParts + 1) * sizeof(unsigned long long);
+
+__device__ __forceinline__ unsigned long long block_sum(unsigned long long v) {
+    __shared__ unsigned long long part[kSumBlock / 64];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (threadIdx.x % 64 == 0) part[threadIdx.x / 64] = v;
+    __syncthreads();
+    unsigned long long total = 0;
+    for (int w = 0; w < kSumBlock / 64; ++w) total += part[w];
+    return total;
+}
+
 __global__ __launch_bounds__(kSumBlock) void k_sum_records(const int32_t* __restrict__ rec,
                                                            int64_t tiles, int word,
-                                                           unsigned long long* __restrict__ out) {
-    __shared__ unsigned long long part[kSumBlock / 64];
+                                                           unsigned long long* __restrict__ parts) {
     unsigned long long s = 0;
-    for (int64_t t = threadIdx.x; t < tiles; t += kSumBlock) s += uint32_t(rec[t * kRec + word]);
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if (threadIdx.x % 64 == 0) part[threadIdx.x / 64] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long total = 0;
-        for (int w = 0; w < kSumBlock / 64; ++w) total += part[w];
-        *out = total;
-    }
+    const int64_t step = int64_t(gridDim.x) * kSumBlock;
+    for (int64_t t = int64_t(blockIdx.x) * kSumBlock + threadIdx.x; t < tiles; t += step)
+        s += uint32_t(rec[t * kRec + word]);
+    const unsigned long long total = block_sum(s);
+    if (threadIdx.x == 0) parts[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kSumBlock) void k_sum_parts(const unsigned long long* __restrict__ parts,
+                                                         int n_parts,
+                                                         unsigned long long* __restrict__ out) {
+    const unsigned long long total = block_sum(threadIdx.x < n_parts ? parts[threadIdx.x] : 0ull);
+    if (threadIdx.x == 0) *out = total;
+}
+
+// Launches the two passes; the total lands in ws[kSumParts].
+lbm_status sum_records(const int32_t* rec, int64_t tiles, int word, unsigned long long* ws,
+                       hipStream_t s) {
+    const int parts = int(std::min<int64_t>(kSumParts, (tiles + kSumBlock - 1) / kSumBlock));
+    k_sum_records<<<parts, kSumBlock, 0, s>>>(rec, tiles, word, ws);
+    if (hipGetLastError() != hipSuccess) return LBM_EHIP;
+    k_sum_parts<<<1, kSumBlock, 0, s>>>(ws, parts, ws + kSumParts);
+    return hipGetLastError() == hipSuccess ? LBM_OK : LBM_EHIP;
 }
 
 constexpr int8_t kNarrowBounce = -128;
@@ -301,21 +327,20 @@ extern "C" lbm_status lbm_compress_adjacency(int64_t n, int64_t stride, const ui
                                              size_t* ws_bytes, void* stream) {
     if (!ws_bytes) return LBM_EINVAL;
     if (!workspace) {
-        *ws_bytes = 256;
+        *ws_bytes = kSumWorkspace;
         return LBM_OK;
     }
-    if (*ws_bytes < 256) return LBM_EWORKSPACE;
+    if (*ws_bytes < kSumWorkspace) return LBM_EWORKSPACE;
     if (lbm_status st = check_layout(n, stride); st != LBM_OK) return st;
     if (!adj || !codes || !tile_records || !n_escapes || n <= 0) return LBM_EINVAL;
     hipStream_t s = as_stream(stream);
-    auto* esc = static_cast<unsigned long long*>(workspace);
+    auto* ws = static_cast<unsigned long long*>(workspace);
     const int64_t tiles = (n + kCTile - 1) / kCTile;
     k_compress<<<dim3(unsigned(tiles)), kCTile, 0, s>>>(adj, n, stride, codes, tile_records);
     if (hipGetLastError() != hipSuccess) return LBM_EHIP;
-    k_sum_records<<<1, kSumBlock, 0, s>>>(tile_records, tiles, Q - 1, esc);
-    if (hipGetLastError() != hipSuccess) return LBM_EHIP;
+    if (lbm_status st = sum_records(tile_records, tiles, Q - 1, ws, s); st != LBM_OK) return st;
     unsigned long long e = 0;
-    LBM_TRY_HIP(hipMemcpyAsync(&e, esc, sizeof(e), hipMemcpyDeviceToHost, s));
+    LBM_TRY_HIP(hipMemcpyAsync(&e, ws + kSumParts, sizeof(e), hipMemcpyDeviceToHost, s));
     LBM_TRY_HIP(hipStreamSynchronize(s));
     *n_escapes = int64_t(e);
     return LBM_OK;
@@ -340,21 +365,20 @@ extern "C" lbm_status lbm_narrow_codes(int64_t n, int64_t stride, const int16_t*
                                        size_t* ws_bytes, void* stream) {
     if (!ws_bytes) return LBM_EINVAL;
     if (!workspace) {
-        *ws_bytes = 256;
+        *ws_bytes = kSumWorkspace;
         return LBM_OK;
     }
-    if (*ws_bytes < 256) return LBM_EWORKSPACE;
+    if (*ws_bytes < kSumWorkspace) return LBM_EWORKSPACE;
     if (lbm_status st = check_layout(n, stride); st != LBM_OK) return st;
     if (!codes || !tile_records || !codes8 || !n_narrow_tiles || n <= 0) return LBM_EINVAL;
     hipStream_t s = as_stream(stream);
-    auto* cnt = static_cast<unsigned long long*>(workspace);
+    auto* ws = static_cast<unsigned long long*>(workspace);
     const int64_t tiles = (n + kCTile - 1) / kCTile;
     k_narrow<<<dim3(unsigned(tiles)), kCTile, 0, s>>>(codes, n, stride, tile_records, codes8);
     if (hipGetLastError() != hipSuccess) return LBM_EHIP;
-    k_sum_records<<<1, kSumBlock, 0, s>>>(tile_records, tiles, Q, cnt);
-    if (hipGetLastError() != hipSuccess) return LBM_EHIP;
+    if (lbm_status st = sum_records(tile_records, tiles, Q, ws, s); st != LBM_OK) return st;
     unsigned long long t = 0;
-    LBM_TRY_HIP(hipMemcpyAsync(&t, cnt, sizeof(t), hipMemcpyDeviceToHost, s));
+    LBM_TRY_HIP(hipMemcpyAsync(&t, ws + kSumParts, sizeof(t), hipMemcpyDeviceToHost, s));
     LBM_TRY_HIP(hipStreamSynchronize(s));
     *n_narrow_tiles = int64_t(t);
     return LBM_OK;
