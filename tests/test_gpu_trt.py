@@ -254,33 +254,41 @@ def sampled_step_vs_oracle(lat, sp, prm, st, advance, ranges, seed):
     return rel_err_f64(got, orc)
 
 
-def test_full_size_tube_sampled_step():
-    """The full 256^3 tube in the benchmark's launch configuration (sweep over
-    16-bit codes, row stride 2^23 + 1024, nontemporal stores, XCD chunk 1):
-    one GPU step from a seeded state compared on sampled cell ranges (head,
-    middle, ragged tail) with the oracle; then 20 more steps conserve mass."""
+@pytest.mark.parametrize("sweep,stride,chunk", [("c8", 8396800, 4), ("c16", 8389632, 1)])
+def test_full_size_tube_sampled_step(sweep, stride, chunk):
+    """The full 256^3 tube in the benchmark's launch configurations (sweep
+    over 8-bit codes in narrow tiles: row stride 2^23 + 8192, nontemporal
+    stores, XCD chunk 4; over 16-bit codes: 2^23 + 1024, chunk 1): one GPU
+    step from a seeded state compared on sampled cell ranges (head, middle,
+    ragged tail) with the oracle; then 20 more steps conserve mass."""
     g = I.packing_tube(2)
-    lat = L.build(dev_flags(g), g.periodic, "lex", stride=8389632)
+    lat = L.build(dev_flags(g), g.periodic, "lex", stride=stride)
     sp = O.build(g.flags, g.periodic, "lex", stride=lat.stride)
     n = lat.n_fluid
     assert n == sp.n_fluid
-    prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), "f64", nontemporal=True, xcd_chunk=1)
-    print_case("tube full size", n)
+    prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), "f64", nontemporal=True, xcd_chunk=chunk)
+    print_case("tube full size", sweep, n)
     comp = L.compress(lat)
+    if sweep == "c8":
+        L.narrow(comp)
+        assert comp.n_narrow > 0.8 * comp.n_tiles
+        advance = lambda k: L.step_c8(st, comp, k)  # noqa: E731
+    else:
+        advance = lambda k: L.step_c16(st, comp, k)  # noqa: E731
     st = L.init(lat, prm)
     ranges = [(0, 4096), (n // 3, n // 3 + 3000), (n // 2 + 17, n // 2 + 5000), (n - 2049, n)]
-    err = sampled_step_vs_oracle(lat, sp, prm, st, lambda: L.step_c16(st, comp, 1), ranges, 10)
+    err = sampled_step_vs_oracle(lat, sp, prm, st, lambda: advance(1), ranges, 10)
     assert err <= TOL_F64
     mass0 = float(st.f[:, :n].sum())
-    L.step_c16(st, comp, 20)
+    advance(20)
     assert abs(float(st.f[:, :n].sum()) - mass0) <= 1e-12 * mass0
 
 
 def test_large_packing_full_size_sampled_step():
     """The 512x512x1024 packing (107 M cells) at full size: one GPU step over
-    16-bit codes from a seeded state, compared on sampled ranges with the
-    oracle (whose sparse representation of the whole box is built on the
-    host)."""
+    8-bit codes (16-bit in the tiles that need them) from a seeded state,
+    compared on sampled ranges with the oracle (whose sparse representation
+    of the whole box is built on the host)."""
     g = I.workload("large_packing")
     lat = L.build(dev_flags(g), g.periodic, "lex")
     n = lat.n_fluid
@@ -288,10 +296,11 @@ def test_large_packing_full_size_sampled_step():
     sp = O.build(g.flags, g.periodic, "lex", stride=lat.stride)
     assert sp.n_fluid == n
     prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), "f64", nontemporal=True, xcd_chunk=64)
-    comp = L.compress(lat)
+    comp = L.narrow(L.compress(lat))
+    assert 0 < comp.n_narrow < comp.n_tiles
     st = L.init(lat, prm)
     ranges = [(0, 4096), (n // 2, n // 2 + 4096), (n - 3001, n)]
-    err = sampled_step_vs_oracle(lat, sp, prm, st, lambda: L.step_c16(st, comp, 1), ranges, 11)
+    err = sampled_step_vs_oracle(lat, sp, prm, st, lambda: L.step_c8(st, comp, 1), ranges, 11)
     assert err <= TOL_F64
     del st, comp, lat, sp
     torch.cuda.empty_cache()
