@@ -127,11 +127,20 @@ def parse():
     return ap.parse_args()
 
 
+def code_only(text: str) -> str:
+    """C++ source with comments, trailing blanks and empty lines removed."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+
+
 def kernel_source_hash(kind: str) -> str:
+    """Hash of the sweep's code (kernel file + device header, comments
+    ignored): a profile summary is trusted only while it matches."""
     h = hashlib.sha256()
     for rel in kernel_sources(kind):
-        with open(os.path.join(ROOT, rel), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, rel)) as fh:
+            h.update(code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

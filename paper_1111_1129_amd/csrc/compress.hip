@@ -1,5 +1,5 @@
-// compress.hip -- 16-bit adjacency codes and the sweep that reads them
-// (lbm_compress_adjacency, lbm_step_c16).
+// compress.hip -- 16-bit and 8-bit adjacency codes and the sweeps that read
+// them (lbm_compress_adjacency, lbm_step_c16, lbm_narrow_codes, lbm_step_c8).
 //
 // The adjacency list is 72 of the 376 bytes a FP64 cell update moves (49 %
 // of the 148 bytes in shifted FP16).  In a locality-preserving ordering the
@@ -10,8 +10,8 @@
 //   code  = ESCAPE (-32767)           if the difference does not fit,
 // with one int32 offset toff per tile and direction (the midpoint of the
 // tile's smallest and largest src - m).  A tile record holds the 18 offsets,
-// the number of escapes in the tile and a zero word (80 bytes, two scalar
-// loads).  The sweep rebuilds the exact slot i*stride + src from the codes
+// the number of escapes in the tile and a flag word, 0 until lbm_narrow_codes
+// sets it (80 bytes, two scalar loads).  The sweep rebuilds the exact slot i*stride + src from the codes
 // (bounce-back: opp(i)*stride + m) in a tile without escapes, and reads the
 // full list in a tile with any: the choice is uniform over the workgroup, so
 // neither path branches per lane and every gather of a cell is in flight at
