@@ -188,7 +188,7 @@ def adjoint(a):
         del lat, comp
     S_best, nt_best, chunk_best, _ = min(table, key=lambda r: r[3])
     lat = L.build(flags, g.periodic, "lex", stride=S_best)
-    comp = L.compress(lat)
+    comp = L.narrow(L.compress(lat))
     n, S = lat.n_fluid, lat.stride
     cell = lat.cell_of.cpu().numpy()
     ns_host = np.zeros(S)
@@ -607,7 +607,7 @@ def oracle_rates(a):
 def pbb(a):
     """The sweep with partial bounce-back (one more FP64 value per cell: the
     solid fraction) on the tube with a uniform random field and on the PBB box
-    with its smoothed field: full list and 16-bit codes."""
+    with its smoothed field: full list, 16-bit and 8-bit codes."""
     cases = [("tube_packing", I.packing_tube(2), None), ("pbb_box 128^3", I.pbb_box(4), "field")]
     sweeps = 400
     for name, g, kind in cases:
@@ -624,21 +624,23 @@ def pbb(a):
                                     generator=torch.Generator().manual_seed(7)).cuda()
             prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), storage, nontemporal=lay.nontemporal,
                            xcd_chunk=lay.xcd_chunk)
-            comp = L.compress(lat)
+            comp = L.narrow(L.compress(lat))  # word 19 is read by the c8 sweep only
+            narrow, escape = code_mix(comp)
             res = {}
-            for sweep in ("full", "c16"):
+            for sweep in ("full", "c16", "c8"):
                 st = L.init(lat, prm, ns=ns)
-                run = (lambda k: L.step(st, k)) if sweep == "full" else \
-                    (lambda k: L.step_c16(st, comp, k))
-                run(2)
-                t, _ = timed(lambda: run(sweeps))
-                byt = 384.0 if sweep == "full" else 348 + 80 / 256
+                step = {"full": lambda k: L.step(st, k), "c16": lambda k: L.step_c16(st, comp, k),
+                        "c8": lambda k: L.step_c8(st, comp, k)}[sweep]
+                step(2)
+                t, _ = timed(lambda: step(sweeps))
+                byt = sweep_bytes(storage, sweep, narrow, escape) + 8  # + the solid fraction
                 res[sweep] = {"mflups": round(n * sweeps / t / 1e6, 1),
                               "bytes_per_update": round(byt, 2),
                               "hbm_frac": round(byt * n * sweeps / t / 1e9 / PEAK, 4)}
                 del st
             emit({"experiment": "pbb", "workload": name, "n_fluid": n, "storage": storage,
-                  "sweeps": sweeps, "layout": [lay.stride, lay.nontemporal, lay.xcd_chunk], **res})
+                  "sweeps": sweeps, "layout": [lay.stride, lay.nontemporal, lay.xcd_chunk],
+                  "narrow_cells": round(narrow, 4), "escape_cells": round(escape, 4), **res})
             del lat, comp, ns
             torch.cuda.empty_cache()
 

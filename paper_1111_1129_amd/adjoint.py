@@ -14,23 +14,30 @@ from __future__ import annotations
 import torch
 
 from . import _native as N
-from .lattice import Compressed, Lattice, compress, init, moments, step_c16
+from .lattice import Compressed, Lattice, compress, init, moments, narrow, step_c8
+
+
+def codes_of(lat: Lattice, comp: Compressed | None) -> Compressed:
+    """The lattice's 16-bit codes with their 8-bit form (built if not given)."""
+    comp = compress(lat) if comp is None else comp
+    return narrow(comp) if comp.codes8 is None else comp
 
 
 def forward_states(lat: Lattice, prm, ns: torch.Tensor, T: int, k: int,
                    comp: Compressed | None = None):
     """Run T steps from rest; return (J, checkpoints at 0, k, 2k, ..., final state).
 
-    The sweeps read the 16-bit adjacency codes (bitwise the same states as
-    the sweep over the full list, fewer bytes)."""
-    comp = compress(lat) if comp is None else comp
+    The sweeps read the 8-bit adjacency codes where a tile allows them and
+    the 16-bit codes elsewhere (bitwise the same states as the sweep over the
+    full list, fewer bytes)."""
+    comp = codes_of(lat, comp)
     st = init(lat, prm, ns=ns)
     ckpts = []
     t = 0
     while t < T:
         ckpts.append(st.f.clone())
         n = min(k, T - t)
-        step_c16(st, comp, n)
+        step_c8(st, comp, n)
         t += n
     _, _, totals = moments(st, fields=False)
     J = totals[0, 1] / lat.n_fluid
@@ -40,8 +47,9 @@ def forward_states(lat: Lattice, prm, ns: torch.Tensor, T: int, k: int,
 def adjoint_gradient(lat: Lattice, prm, ns: torch.Tensor, T: int, k: int, ckpts=None,
                      comp: Compressed | None = None):
     """dJ/dns [stride] (float64) by checkpointed reverse sweeps (the segment
-    recomputation and the adjoint steps read the 16-bit adjacency codes)."""
-    comp = compress(lat) if comp is None else comp
+    recomputation reads the 8-/16-bit codes as the forward does, the adjoint
+    steps the 16-bit codes)."""
+    comp = codes_of(lat, comp)
     if ckpts is None:
         _, ckpts, _ = forward_states(lat, prm, ns, T, k, comp)
     S, n = lat.stride, lat.n_fluid
@@ -57,9 +65,9 @@ def adjoint_gradient(lat: Lattice, prm, ns: torch.Tensor, T: int, k: int, ckpts=
         t1 = min(t0 + k, T)
         buf[0].copy_(ckpts[s])
         for j in range(1, t1 - t0):
-            st = N.lbm_step_c16(prm, n, S, comp.codes, comp.tile_records, lat.adj, ns,
-                                buf[j - 1], buf[j], 1)
-            N._check("lbm_step_c16", st)
+            st = N.lbm_step_c8(prm, n, S, comp.codes8, comp.codes, comp.tile_records, lat.adj,
+                               ns, buf[j - 1], buf[j], 1)
+            N._check("lbm_step_c8", st)
         for t in range(t1 - 1, t0 - 1, -1):
             rc = N.lbm_step_adjoint_c16(prm, n, S, comp.codes, comp.tile_records, lat.adj,
                                         buf[t - t0], ns, lam, lam_prev, grad)

@@ -165,6 +165,30 @@ def test_batched_equals_solo():
         np.testing.assert_array_equal(tot[k].cpu().numpy(), ts[0].cpu().numpy())
 
 
+def test_batched_over_codes_equals_per_step():
+    """A lexicographic batch of uneven packings swept over 16-bit and over
+    8-bit codes (tiles straddling two members included) ends in the state of
+    the full-list sweep, two arrays and in place."""
+    geoms = [I.packing_boolean(60 + k, L_, L_, L_, 2.0, 4.0, p)
+             for k, (L_, p) in enumerate([(40, 0.5), (33, 0.4), (21, 0.6), (48, 0.45)])]
+    batch = L.Batch([dev_flags(g) for g in geoms], [g.periodic for g in geoms], "lex")
+    print_case("batched codes", batch.total)
+    prm = L.params(0.8, 3 / 16, (1e-5, 0, 0), "f32s")
+    ref = batch.init(prm)
+    L.step(ref, 12)
+    comp = L.compress(batch.lattice, n=batch.total)
+    s16 = batch.init(prm)
+    L.step_c16(s16, comp, 12)
+    L.narrow(comp)
+    assert comp.n_narrow > 0
+    s8 = batch.init(prm)
+    L.step_c8(s8, comp, 12)
+    one = L.init_inplace(batch.lattice, prm, n=batch.total)
+    L.step_inplace(one, 12, comp, c8=True)
+    for st in (s16, s8, one):
+        assert torch.equal(st.f[:, :batch.total], ref.f[:, :batch.total])
+
+
 def test_adjoint_vs_central_differences_full_size():
     """128^3 box with a partial-bounce-back field, 500 shifted-FP64 steps,
     checkpoints every 22 steps: the adjoint gradient of the mean flux matches
