@@ -37,7 +37,7 @@ def compile_flags() -> list[str]:
             # a*b+c is fused only inside one source expression: which products
             # the compiler fuses then does not depend on the code around the
             # collision, so every kernel that inlines it (one launch per step,
-            # persistent, 16-bit codes) rounds identically
+            # persistent, over adjacency codes, in place) rounds identically
             "-ffp-contract=on",
             f"-I{INCLUDE}", f"-I{CSRC}"]
 
