@@ -159,9 +159,6 @@ lbm_status sum_records(const int32_t* rec, int64_t tiles, int word, unsigned lon
     return hipGetLastError() == hipSuccess ? LBM_OK : LBM_EHIP;
 }
 
-constexpr int8_t kNarrowBounce = -128;
-constexpr int32_t kNarrowMax = 127;
-
 // One workgroup per tile: the tile is narrow if every live cell's 18 codes
 // fit (a tile with escapes never does).  Codes of a wide tile are stored as 0.
 __global__ __launch_bounds__(kCTile) void k_narrow(const int16_t* __restrict__ codes, int64_t n,
@@ -177,13 +174,13 @@ __global__ __launch_bounds__(kCTile) void k_narrow(const int16_t* __restrict__ c
     bool fits = true;
 #pragma unroll
     for (int k = 0; k < Q - 1; ++k)
-        fits = fits && (cd[k] == kCodeBounce || (cd[k] >= -kNarrowMax && cd[k] <= kNarrowMax));
+        fits = fits && (cd[k] == kCodeBounce || (cd[k] >= -kCode8Max && cd[k] <= kCode8Max));
     const bool narrow = __syncthreads_and(!live || fits) != 0;  // every thread takes part
     if (live) {
 #pragma unroll
         for (int k = 0; k < Q - 1; ++k)
             codes8[k * stride + m] =
-                narrow ? (cd[k] == kCodeBounce ? kNarrowBounce : int8_t(cd[k])) : int8_t(0);
+                narrow ? (cd[k] == kCodeBounce ? kCode8Bounce : int8_t(cd[k])) : int8_t(0);
     }
     if (threadIdx.x == 0) rec[tile * kRec + Q] = narrow ? 1 : 0;
 }
@@ -201,7 +198,7 @@ __device__ __forceinline__ void update_cell_coded(const typename Storage<ST>::T*
                                                   int64_t stride, const TrtConst& c) {
     using T = typename Storage<ST>::T;
     using A = typename Storage<ST>::A;
-    constexpr int32_t bounce = std::is_same_v<CT, int8_t> ? int32_t(kNarrowBounce)
+    constexpr int32_t bounce = std::is_same_v<CT, int8_t> ? int32_t(kCode8Bounce)
                                                           : int32_t(kCodeBounce);
     int32_t cd[Q - 1];
     const CT* cp = codes + m;

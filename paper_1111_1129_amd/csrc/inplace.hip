@@ -35,7 +35,6 @@ constexpr int kIBlock = kCodeTile;  // a workgroup is one tile of the codes
 
 // Where the gather-scatter step finds a cell's slots.
 enum SlotSource { kFromAdj = 0, kFrom16 = 1, kFrom8 = 2 };
-constexpr int32_t kBounce8 = -128;  // bounce-back in the 8-bit codes
 
 // Slots rebuilt from the 16-bit (SRC = kFrom16) or 8-bit (kFrom8) codes of
 // the cell's tile: s[k] = adj(k + 1, m).
@@ -43,7 +42,7 @@ template <int SRC, class CT>
 __device__ __forceinline__ void slots_from_codes(uint32_t* s, const CT* __restrict__ codes,
                                                  const int32_t* __restrict__ rec, int64_t m,
                                                  int64_t stride) {
-    constexpr int32_t bounce = SRC == kFrom8 ? kBounce8 : int32_t(kCodeBounce);
+    constexpr int32_t bounce = SRC == kFrom8 ? int32_t(kCode8Bounce) : int32_t(kCodeBounce);
     const CT* cp = codes + m;
     int32_t cd[Q - 1];
 #pragma unroll

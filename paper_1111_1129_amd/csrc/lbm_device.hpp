@@ -44,7 +44,7 @@ template <> struct Storage<LBM_F32_SHIFTED> { using T = float; using A = float; 
 template <> struct Storage<LBM_F16_SHIFTED> { using T = _Float16; using A = float; static constexpr bool shifted = true; };
 
 template <class T, class A> __device__ __forceinline__ A ld(const T* p) { return static_cast<A>(*p); }
-// Read-once streams (adjacency rows, 16-bit codes): nontemporal loads keep
+// Read-once streams (adjacency rows, adjacency codes): nontemporal loads keep
 // them from displacing the PDF lines whose partial reuse by neighbouring
 // cells the caches serve (measured: 2 % faster sweep over codes in FP64).
 template <class T> __device__ __forceinline__ T ld_stream(const T* p) {
@@ -74,13 +74,18 @@ inline size_t storage_bytes(int st) {
 
 // 16-bit adjacency codes (lbm_compress_adjacency): tiles of 256 list cells,
 // one record of 20 int32 words per tile (18 direction offsets, the number of
-// escape codes in the tile, a zero word); reserved code values.
+// escape codes in the tile, the narrow flag of lbm_narrow_codes); reserved
+// code values.
 constexpr int kCodeTile = 256;
 constexpr int kCodeRec = 20;
 constexpr int16_t kCodeBounce = -32768;
 constexpr int16_t kCodeEscape = -32767;
 constexpr int32_t kCodeMin = -32766;
 constexpr int32_t kCodeMax = 32767;
+// 8-bit form of a tile's codes (lbm_narrow_codes): the same code in one byte,
+// bounce-back as -128.
+constexpr int8_t kCode8Bounce = -128;
+constexpr int32_t kCode8Max = 127;
 
 // ---------------------------------------------------------------------------
 // TRT constants of one launch (host-computed in FP64).
