@@ -649,7 +649,8 @@ def pbb(a):
 def launch_overhead(a):
     """Where the persistent launch pays: geometries small enough that a sweep
     takes about as long as launching it (the 32^3 packing, 17 k cells) up to
-    the tube (7.8 M cells); one launch per step vs one persistent launch."""
+    the tube (7.8 M cells); one launch per step vs one persistent launch vs
+    the per-step launches captured once in a HIP graph and replayed."""
     cases = [("small_packing", I.packing_small(1), 4000),
              ("packing_64", I.packing_small(1, n=64, radius=8.0), 2000),
              ("packing_128", I.packing_small(1, n=128, radius=16.0), 1000),
@@ -666,6 +667,20 @@ def launch_overhead(a):
             a2 = L.init(lat, prm)
             L.step(a2, 10, persistent=True)
             t_pers, _ = timed(lambda: L.step(a2, steps, persistent=True))
+            a3 = L.init(lat, prm)
+            L.step(a3, 10)
+            chunk = min(steps, 200)  # steps per captured graph
+            graph = L.StepGraph(a3, chunk)
+            graph.replay()
+
+            def replays():
+                for _ in range(steps // chunk):
+                    graph.replay()
+            t_graph, _ = timed(replays)
+            ref = L.init(lat, prm)  # the same step count eagerly
+            L.step(ref, a3.steps)
+            graph_equal = bool(torch.equal(ref.f[:, :n], a3.f[:, :n]))
+            del ref
             emit({"experiment": "launch_overhead", "workload": name, "n_fluid": n,
                   "storage": storage, "steps": steps,
                   "us_per_step_launch": round(t_step / steps * 1e6, 2),
@@ -673,7 +688,10 @@ def launch_overhead(a):
                   "mflups_launch": round(n * steps / t_step / 1e6, 1),
                   "mflups_persistent": round(n * steps / t_pers / 1e6, 1),
                   "persistent_speedup": round(t_step / t_pers, 3),
-                  "equal": bool(torch.equal(a1.f[:, :n], a2.f[:, :n]))})
-            del a1, a2
+                  "us_per_step_graph": round(t_graph / steps * 1e6, 2),
+                  "graph_speedup": round(t_step / t_graph, 3),
+                  "equal": bool(torch.equal(a1.f[:, :n], a2.f[:, :n])),
+                  "graph_equal": graph_equal})
+            del a1, a2, a3, graph
         del lat
         torch.cuda.empty_cache()

@@ -18,7 +18,7 @@ def __getattr__(name):
     # lazy: keep `import paper_1111_1129_amd.inputs` free of torch and HIP
     if name in ("build", "init", "step", "moments", "params", "set_state", "count_fluid",
                 "partition_stats", "aligned_stride", "Lattice", "State", "Batch",
-                "compress", "step_c16", "narrow", "step_c8", "Compressed", "InplaceState",
+                "compress", "step_c16", "narrow", "step_c8", "Compressed", "StepGraph", "InplaceState",
                 "init_inplace", "step_inplace"):
         from . import lattice
         return getattr(lattice, name)

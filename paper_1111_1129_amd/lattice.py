@@ -275,6 +275,47 @@ def step_c16(state: State, comp: Compressed, n_steps: int = 1, stream=None):
     return state
 
 
+class StepGraph:
+    """n_steps sweeps of a State captured once in a HIP graph and replayed as
+    one graph launch, for geometries so small that launching a sweep costs
+    about as much as the sweep.  n_steps is even, so each replay leaves the
+    result in state.f.  The sweeps read the full list (comp None), the
+    16-bit codes, or the 8-bit codes where comp has been narrowed; results
+    are bitwise those of the same eager calls.  The captured work is kernel
+    launches only (no allocation, no memset); the buffers and parameters are
+    fixed at capture."""
+
+    def __init__(self, state: State, n_steps: int, comp: Compressed | None = None):
+        assert n_steps > 0 and n_steps % 2 == 0, "an even step count"
+        lat = state.lattice
+        if comp is not None:
+            assert comp.n == state.n and comp.codes.shape[1] == lat.stride
+        self.state, self.n_steps, self.comp = state, n_steps, comp
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):  # launches go to the capturing stream
+            self._launch()
+
+    def _launch(self):
+        st, lat, comp = self.state, self.state.lattice, self.comp
+        if comp is None:
+            rc, _ = N.lbm_step(st.params, st.n, lat.stride, lat.adj, st.ns, st.f, st.g,
+                               self.n_steps)
+            N._check("lbm_step", rc)
+        elif comp.codes8 is None:
+            N._check("lbm_step_c16", N.lbm_step_c16(st.params, st.n, lat.stride, comp.codes,
+                                                    comp.tile_records, lat.adj, st.ns, st.f,
+                                                    st.g, self.n_steps))
+        else:
+            N._check("lbm_step_c8", N.lbm_step_c8(st.params, st.n, lat.stride, comp.codes8,
+                                                  comp.codes, comp.tile_records, lat.adj, st.ns,
+                                                  st.f, st.g, self.n_steps))
+
+    def replay(self) -> State:
+        self.graph.replay()
+        self.state.steps += self.n_steps
+        return self.state
+
+
 @dataclasses.dataclass
 class InplaceState:
     """One PDF array [19][stride] stepped in place (lbm_step_inplace).
