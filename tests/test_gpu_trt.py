@@ -284,26 +284,72 @@ def test_full_size_tube_sampled_step(sweep, stride, chunk):
     assert abs(float(st.f[:, :n].sum()) - mass0) <= 1e-12 * mass0
 
 
-def test_large_packing_full_size_sampled_step():
+@pytest.fixture(scope="module")
+def large():
+    """The 512x512x1024 packing (107 M cells) on the GPU and its oracle
+    sparse representation, built once on the host."""
+    g = I.workload("large_packing")
+    lat = L.build(dev_flags(g), g.periodic, "lex")
+    sp = O.build(g.flags, g.periodic, "lex", stride=lat.stride)
+    assert sp.n_fluid == lat.n_fluid
+    comp = L.narrow(L.compress(lat))
+    assert 0 < comp.n_narrow < comp.n_tiles
+    yield lat, sp, comp
+    del lat, sp, comp
+    torch.cuda.empty_cache()
+
+
+def test_large_packing_full_size_sampled_step(large):
     """The 512x512x1024 packing (107 M cells) at full size: one GPU step over
     8-bit codes (16-bit in the tiles that need them) from a seeded state,
     compared on sampled ranges with the oracle (whose sparse representation
     of the whole box is built on the host)."""
-    g = I.workload("large_packing")
-    lat = L.build(dev_flags(g), g.periodic, "lex")
+    lat, sp, comp = large
     n = lat.n_fluid
     print_case("large packing full size", n)
-    sp = O.build(g.flags, g.periodic, "lex", stride=lat.stride)
-    assert sp.n_fluid == n
     prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), "f64", nontemporal=True, xcd_chunk=64)
-    comp = L.narrow(L.compress(lat))
-    assert 0 < comp.n_narrow < comp.n_tiles
     st = L.init(lat, prm)
     ranges = [(0, 4096), (n // 2, n // 2 + 4096), (n - 3001, n)]
     err = sampled_step_vs_oracle(lat, sp, prm, st, lambda: L.step_c8(st, comp, 1), ranges, 11)
     assert err <= TOL_F64
-    del st, comp, lat, sp
-    torch.cuda.empty_cache()
+    del st
+
+
+@pytest.mark.parametrize("storage", ["f32s", "f16s"])
+def test_large_packing_full_size_sampled_step_reduced(large, storage):
+    """The same in shifted FP32 / FP16 storage (FP32 arithmetic), in the
+    launch configuration of the precision experiment: the oracle computes in
+    FP64 from the same stored values and rounds to the storage type; bound as
+    for the one-step test on the small packing (one storage ulp + 64 eps32 of
+    the largest stored value)."""
+    lat, sp, comp = large
+    n, S = lat.n_fluid, lat.stride
+    print_case("large packing full size", storage, n)
+    prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), storage, nontemporal=True, xcd_chunk=1)
+    st = L.init(lat, prm)
+    dt = np.float16 if storage == "f16s" else np.float32
+    ranges = [(0, 4096), (n // 3, n // 3 + 3000), (n - 2049, n)]
+    cells_ = np.concatenate([np.arange(a, b) for a, b in ranges]).astype(np.int64)
+    k = cells_.size
+    slots = np.empty((19, k), dtype=np.int64)
+    slots[0] = cells_
+    slots[1:] = sp.adj[:, cells_].astype(np.int64)
+    rng = np.random.default_rng(12)
+    vals = (W[slots // S] * 2e-2 * rng.standard_normal(slots.shape)).astype(dt)  # h = f - w
+    st.f.zero_()  # shifted rest state everywhere
+    st.f.view(-1)[torch.from_numpy(slots.ravel()).cuda()] = torch.from_numpy(vals.ravel()).cuda()
+    L.step_c8(st, comp, 1)
+    got = st.f[:, torch.from_numpy(cells_).cuda()].cpu().numpy().astype(np.float64)
+    ident = ((np.arange(1, 19, dtype=np.uint64)[:, None] * k + np.arange(k, dtype=np.uint64)[None, :])
+             .astype(np.uint32))
+    exact = np.zeros((19, k))
+    O.step(oracle_params(prm), ident, np.ascontiguousarray(vals.astype(np.float64)), exact)
+    orc = O.round_storage(exact, storage)
+    ulp = np.spacing(np.abs(exact).astype(dt)).astype(np.float64)
+    tol = ulp + 64 * np.finfo(np.float32).eps * np.abs(vals.astype(np.float64)).max()
+    assert (np.abs(got - orc) <= tol).all()
+    assert np.abs(got - vals.astype(np.float64)).max() > 10 * tol.max()  # it moved
+    del st
 
 
 def test_large_packing_cropped_vs_oracle():
