@@ -189,6 +189,47 @@ def test_batched_over_codes_equals_per_step():
         assert torch.equal(st.f[:, :batch.total], ref.f[:, :batch.total])
 
 
+def test_batch_full_size_persistent_step_vs_oracle():
+    """The 64-packing batch of the batched experiment (38.4 M cells) at full
+    size, one persistent-launch FP32 step from a seeded state: the head and
+    the ragged tail of every member against the oracle.  The slots each
+    sampled cell reads come from the oracle's own adjacency of the member,
+    placed at the member's columns; FP32 bound as for the one-step test of
+    the small packing (one FP32 ulp + 64 eps32)."""
+    from gpu_helpers import W
+    geoms = I.batch_packings()
+    batch = L.Batch([dev_flags(g) for g in geoms], [g.periodic for g in geoms], "lex")
+    lat, S = batch.lattice, batch.lattice.stride
+    print_case("batch full size", len(geoms), batch.total)
+    cells, slots = [], []
+    for g, (base, cnt) in zip(geoms, batch.segments):
+        sp = O.build(g.flags, g.periodic, "lex")
+        assert sp.n_fluid == cnt
+        Sk = sp.adj.shape[1]
+        m = np.concatenate([np.arange(0, min(256, cnt)), np.arange(max(cnt - 200, 256), cnt)])
+        a = sp.adj[:, m].astype(np.int64)
+        cells.append(base + m)
+        slots.append(np.vstack([base + m, (a // Sk) * S + base + a % Sk]))
+    cells = np.concatenate(cells)
+    slots = np.concatenate(slots, axis=1)
+    k = cells.size
+    rng = np.random.default_rng(21)
+    vals = (W[slots // S] * (1.0 + 0.02 * rng.standard_normal(slots.shape))).astype(np.float32)
+    prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), "f32", nontemporal=True, xcd_chunk=16)
+    st = batch.init(prm)
+    st.f.copy_(torch.from_numpy(W.astype(np.float32)).cuda()[:, None].expand(19, S))
+    st.f.view(-1)[torch.from_numpy(slots.ravel()).cuda()] = torch.from_numpy(vals.ravel()).cuda()
+    L.step(st, 1, persistent=True, segments=batch.segments)
+    got = st.f[:, torch.from_numpy(cells).cuda()].cpu().numpy().astype(np.float64)
+    ident = ((np.arange(1, 19, dtype=np.uint64)[:, None] * k + np.arange(k, dtype=np.uint64)[None, :])
+             .astype(np.uint32))
+    exact = np.zeros((19, k))
+    O.step(oracle_params(prm), ident, np.ascontiguousarray(vals.astype(np.float64)), exact)
+    orc = O.round_storage(exact, "f32")
+    tol = np.spacing(np.abs(exact).astype(np.float32)).astype(np.float64) + 64 * np.finfo(np.float32).eps
+    assert (np.abs(got - orc) <= tol).all()
+
+
 def test_adjoint_vs_central_differences_full_size():
     """128^3 box with a partial-bounce-back field, 500 shifted-FP64 steps,
     checkpoints every 22 steps: the adjoint gradient of the mean flux matches
