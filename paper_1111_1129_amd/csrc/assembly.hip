@@ -385,7 +385,7 @@ extern "C" lbm_status lbm_build_adjacency(const lbm_geom* g, const uint8_t* flag
     if (*ws_bytes < need) return LBM_EWORKSPACE;
     if (!flag || !n_fluid) return LBM_EINVAL;
     if (base < 0 || cap < 0) return LBM_EINVAL;
-    if (adj && (stride < 0 || 19 * stride >= kIndexLimit)) return LBM_EOVERFLOW;
+    if (adj && !stride_fits(stride)) return LBM_EOVERFLOW;
 
     char* ws = static_cast<char*>(workspace);
     uint32_t* tile_count = reinterpret_cast<uint32_t*>(ws);

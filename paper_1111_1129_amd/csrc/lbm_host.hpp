@@ -42,10 +42,14 @@ inline bool valid_params(const lbm_params* p) {
     return true;
 }
 
+// 19 * stride < 2^32, tested without forming the product (a caller's
+// stride near INT64_MAX would overflow it).
+inline bool stride_fits(int64_t stride) { return stride >= 0 && stride <= (kIndexLimit - 1) / 19; }
+
 // Layout checks common to every call that touches [19][stride] arrays.
 inline lbm_status check_layout(int64_t n, int64_t stride) {
     if (n < 0 || stride < n || stride < 0) return LBM_EINVAL;
-    if (19 * stride >= kIndexLimit) return LBM_EOVERFLOW;
+    if (!stride_fits(stride)) return LBM_EOVERFLOW;
     return LBM_OK;
 }
 

@@ -103,6 +103,13 @@ def test_host_side_argument_errors(lib):
     assert step(good, n_params=2) == N.LBM_EINVAL
     assert step(good, a=dummy, b=dummy) == N.LBM_EINVAL              # in-place not allowed
     assert step(good, n=10, stride=(1 << 32) // 19 + 1) == N.LBM_EOVERFLOW
+    # strides whose product with 19 would overflow int64 are refused, not wrapped
+    for big in ((1 << 63) - 1, (1 << 63) // 2, (1 << 63) // 19 + 1):
+        assert step(good, n=10, stride=big) == N.LBM_EOVERFLOW
+        g = N.lbm_geom(4, 4, 4, 0, 0, 0)
+        ws = C.c_size_t(1 << 20)
+        assert lib.lbm_build_adjacency(C.byref(g), P(4096), 0, big, None, P(4096), P(4096), 64,
+                                       C.byref(nf), P(4096), C.byref(ws), None) == N.LBM_EOVERFLOW
     # persistent size query
     ws = C.c_size_t(0)
     assert lib.lbm_step(C.byref(good), 1, None, 0, 10, 10, dummy, None, dummy, P(8192), 5, 1,

@@ -167,6 +167,17 @@ def test_splitmix64_definition():
     assert len(outs) == 4096
 
 
+def test_splitmix64_published_outputs():
+    """The published SplitMix64 stream from state 0 (tests/golden): any change
+    to a constant or shift of the generator changes these outputs."""
+    gamma = 0x9E3779B97F4A7C15
+    rows = [ln.split() for ln in open(os.path.join(GOLDEN, "splitmix64_seed0.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    assert len(rows) == 5
+    for k, out in rows:
+        assert O.splitmix64(int(k) * gamma % 2 ** 64) == int(out, 16)
+
+
 def test_ranks_increase_with_key():
     g = I.random_flags(5, 9, 7, 6, periodic=1)
     for order, param in [("lex", 0), ("blocked", 4), ("morton1", 0), ("morton2", 0),
