@@ -2,29 +2,35 @@
 
 One benchmark "step" is one pass of the whole hot path over the workload:
 assembly of the sparse representation from the flag field (numbering,
-compaction, adjacency), equilibrium initialisation, SWEEPS pull sweeps, and
-the FP64 moments/totals of the final state.  The flag field is resident in
-HBM before the timed region.  value = fluid-lattice updates per second of the
-whole job (MFLUPS, counting fluid cells only).
+compaction, adjacency, adjacency codes), equilibrium initialisation, SWEEPS
+pull sweeps, and the FP64 moments/totals of the final state.  The flag field
+is resident in HBM before the timed region.  value = fluid-lattice updates per
+second of the whole job (MFLUPS, counting fluid cells only, as the paper's
+FLUP/s in Sec. 7), in double precision.
 
-Default workload: 256^3 tube (diameter 240) packed with radius-12 spheres by
-seeded random sequential addition, periodic in x, force-driven, D3Q19 TRT with
-tau+ = 0.8, magic 3/16, 1000 sweeps, FP64 storage, lexicographic ordering.
-The sweep reads the adjacency as 8-bit codes in the tiles whose codes fit a
-byte and as 16-bit codes elsewhere (``--sweep c8``: the codes are built inside
-the step; results are bitwise those of the sweep over the full uint32 list,
-``--sweep full``); ``c16`` reads 16-bit codes only; ``inplace`` /
-``inplace_c16`` / ``inplace_c8`` step one PDF array instead of two.
+Default workload (the precision configuration): a 512 x 512 x 1024 box with
+1-cell walls on the y and z faces, periodic in x, filled with overlapping
+spheres of radius uniform in [8, 16] to porosity 0.40 (seed 3,
+107,371,203 fluid cells), D3Q19 TRT with tau+ = 0.8, magic 3/16, body force
+g_x = 1e-6, 500 sweeps from rest, FP64 storage, lexicographic ordering.  The
+sweep reads the adjacency as 8-bit codes in the tiles whose codes fit a byte
+and as 16-bit codes elsewhere (``--sweep c8``; results are bitwise those of
+the sweep over the full uint32 list, ``--sweep full``).
 
-Experiments (``--experiment``, one JSON line per configuration, see
-bench_experiments.py): precision (FP64 / FP32 / shifted FP16 storage on the
-512x512x1024 packing, speed-up and velocity error), adjoint (gradient of the
-mean flux w.r.t. a partial-bounce-back field, checked against central
-differences), batched (64 uneven geometries, one persistent launch vs one
-launch per step vs separate launches), orderings (lexicographic, blocking
-factors, Z curves, random on the tube), partitions (neighbour chunks and
-remote links of a list cut into G chunks), ordering_tuner, compressed (sweep
-over 16-bit and 8-bit adjacency codes vs the full list).
+After the timed loop the same 500 sweeps run once in every other storage
+form (shifted FP64, FP32, shifted FP32, shifted FP16 with FP32 arithmetic);
+the line's ``precision`` object gives each form's sweep rate, its speed-up
+over the FP64 sweep and the relative L2 and max error of its velocity field
+against the FP64 run's.  At this size the parity-checked FP64 GPU run stands
+in for the oracle (its host arrays would need about 42 GB and hours); the
+oracle itself runs 500 sweeps of a central crop of the same flag field (the
+CPU baseline) and every form's error against it on that crop is reported too.
+
+``--workload tube_packing`` runs the 256^3 tube of the ordering study instead
+(1000 sweeps).  Experiments (``--experiment``, one JSON line per
+configuration, see bench_experiments.py): precision (all forms at three force
+levels), adjoint, batched, orderings, partitions, ordering_tuner, compressed,
+oracle_rates, pbb, launch_overhead.
 
 Besides the one JSON line the run reports, for the dominant kernel (the
 sweep), the achieved HBM bandwidth from its algorithmic bytes (19 PDFs read +
@@ -96,9 +102,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="tube_packing",
+    ap.add_argument("--workload", default="large_packing",
                     choices=["tube_packing", "small_packing", "large_packing", "channel"])
-    ap.add_argument("--sweeps", type=int, default=1000)
+    ap.add_argument("--sweeps", type=int, default=0,
+                    help="sweeps per pass (0: 500 for large_packing, else 1000)")
+    ap.add_argument("--precision", type=int, default=1,
+                    help="after the timed loop run the other storage forms once and report "
+                         "speed-up and velocity error vs FP64 (headline only)")
     ap.add_argument("--order", default="lex")
     ap.add_argument("--param", type=int, default=0)
     ap.add_argument("--storage", default="f64", choices=list(BYTES_PER_FLUP))
@@ -121,7 +131,8 @@ def parse():
                     help="headline: the JSON line below; the others print one JSON line per "
                          "configuration (see the module docstring)")
     ap.add_argument("--scale", type=int, default=1,
-                    help="experiments: divide workload edge lengths by this (quick checks)")
+                    help="divide the large packing's (and the experiments' workloads') edge "
+                         "lengths by this (quick checks)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample (0 = skip)")
     return ap.parse_args()
@@ -162,46 +173,162 @@ def traffic_from_profile(kind: str, workload: str, order: str, storage: str):
     return float(m_bytes.group(1))
 
 
-def make_workload(name: str):
+def make_workload(name: str, scale: int = 1):
     from paper_1111_1129_amd import inputs as I
+    if name == "large_packing" and scale > 1:  # edges and radii divided by scale
+        return (I.workload("large_packing", scale=scale),
+                f"{512 // scale}x{512 // scale}x{1024 // scale} box, walls y/z, periodic x, "
+                f"overlapping spheres r~U[{8 / scale:g},{16 / scale:g}] to porosity 0.40, seed 3")
     if name == "tube_packing":
         return I.packing_tube(2), "256^3 tube D=240, RSA spheres r=12, seed 2"
     if name == "small_packing":
         return I.packing_small(1), "32^3 box, RSA spheres r=4, seed 1"
     if name == "large_packing":
-        return I.workload("large_packing"), "512x512x1024 Boolean spheres r~U[8,16], porosity 0.4"
+        return (I.workload("large_packing"),
+                "512x512x1024 box, walls y/z, periodic x, overlapping spheres r~U[8,16] "
+                "to porosity 0.40, seed 3")
     if name == "channel":
         return I.channel(100), "500x100x100 empty channel"
     raise KeyError(name)
 
 
-def cpu_baseline(geom, order, param, storage, target_s, n_ref):
-    """Oracle sweep timed on the host cores on a bounded number of sweeps."""
+def central_crop(flags: np.ndarray, edge_div: int) -> np.ndarray:
+    """Central sub-box with every edge divided by edge_div (a sample of the
+    same flag field for the oracle)."""
+    nz, ny, nx = flags.shape
+    sz, sy, sx = max(1, nz // edge_div), max(1, ny // edge_div), max(1, nx // edge_div)
+    z0, y0, x0 = (nz - sz) // 2, (ny - sy) // 2, (nx - sx) // 2
+    return np.ascontiguousarray(flags[z0:z0 + sz, y0:y0 + sy, x0:x0 + sx])
+
+
+def cpu_baseline(geom, order, param, storage, target_s, crop_div=1, sweeps=0):
+    """The oracle's FP64 sweep timed on the host cores.
+
+    crop_div == 1: sweeps of the whole geometry until target_s has passed.
+    crop_div > 1: exactly `sweeps` sweeps from rest of the central crop with
+    every edge divided by crop_div (the full geometry's host arrays would not
+    fit a bounded sample); the oracle's final state is returned as well, for
+    the reduced-precision forms' error on the same crop.
+    Returns (baseline dict, (crop flags, oracle sparse, oracle state) or None)."""
     import oracle as O
-    sp = O.build(geom.flags, geom.periodic, order, param)
+    flags = geom.flags if crop_div == 1 else central_crop(geom.flags, crop_div)
+    sp = O.build(flags, geom.periodic, order, param)
     prm = O.TRT(0.8, 3.0 / 16.0, (1e-6, 0.0, 0.0))
     f = O.init(sp.n_fluid, shifted=storage.endswith("s"))
     g = np.empty_like(f)
     O.step(prm, sp.adj, f, g)  # warm (page-in)
+    f = O.init(sp.n_fluid, shifted=storage.endswith("s"))
     steps = 0
     t0 = time.perf_counter()
     while True:
         O.step(prm, sp.adj, f, g)
         f, g = g, f
         steps += 1
-        if time.perf_counter() - t0 >= target_s:
+        if (sweeps and steps >= sweeps) or (not sweeps and time.perf_counter() - t0 >= target_s):
             break
     dt = time.perf_counter() - t0
-    return {"value": sp.n_fluid * steps / dt / 1e6, "unit": "MFLUPS", "cores": O.max_threads(),
-            "kind": "oracle",
-            "sample": f"{steps} FP64 sweeps of the same geometry ({sp.n_fluid} fluid cells, "
-                      f"{order}), {dt:.1f} s, OpenMP over cells"}
+    if crop_div == 1:
+        sample = (f"{steps} FP64 sweeps of the same geometry ({sp.n_fluid} fluid cells, "
+                  f"{order}), {dt:.1f} s, OpenMP over cells")
+    else:
+        nz, ny, nx = flags.shape
+        sample = (f"{steps} FP64 sweeps from rest of the central {nx}x{ny}x{nz} crop of the "
+                  f"same flag field (1/{crop_div ** 3} of the box, {sp.n_fluid} fluid cells, "
+                  f"{order}), {dt:.1f} s, OpenMP over cells")
+    base = {"value": round(sp.n_fluid * steps / dt / 1e6, 2), "unit": "MFLUPS",
+            "cores": O.max_threads(), "kind": "oracle", "sample": sample}
+    return base, (None if crop_div == 1 else (flags, sp, f, prm))
+
+
+def rel_errors(u, ref):
+    """(relative L2, max |u - ref| / max |ref|) of two [3][n] velocity fields."""
+    import torch
+    d = u - ref
+    return (float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(ref)),
+            float(d.abs().max() / ref.abs().max()))
+
+
+def run_form(flags, geom, a, storage, kind, sweeps, layout=None):
+    """One storage form: tune its layout (unless given), sweep `sweeps` times
+    from rest, return (seconds per sweep, u [3][n] FP64, Layout)."""
+    import torch
+    from paper_1111_1129_amd import lattice as L
+    from paper_1111_1129_amd.tune import Layout, Sweeper, tune_layout
+    if layout is None:
+        layout = (tune_layout(flags, geom.periodic, a.order, a.param, storage, sweep=kind)
+                  if a.layout == "tuned" else Layout(None, False, 0))
+    lat = L.build(flags, geom.periodic, a.order, a.param, stride=layout.stride)
+    sw = Sweeper(lat, kind)
+    prm = L.params(0.8, 3.0 / 16.0, (1e-6, 0.0, 0.0), storage, nontemporal=layout.nontemporal,
+                   xcd_chunk=layout.xcd_chunk)
+    st = sw.init(prm)
+    sw.step(st, 2)
+    st = sw.init(prm)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    sw.step(st, sweeps)
+    e1.record(stream)
+    e1.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / sweeps
+    _, u, _ = L.moments(st)
+    narrow, escape = code_mix(sw.comp)
+    bpf = sweep_bytes(storage, kind, narrow, escape)
+    del st, sw, lat
+    return t, u, layout, bpf
+
+
+def precision_leg(flags, geom, a, sweeps, u_ref, t_ref):
+    """Every other storage form once over the same sweeps: rate, speed-up over
+    the FP64 sweep, velocity error vs the FP64 run."""
+    import torch
+    forms = {}
+    for storage in ("f64s", "f32", "f32s", "f16s"):
+        kinds = (a.sweep,) if storage.startswith("f64") else (a.sweep, "inplace_c8")
+        rec = {}
+        for kind in dict.fromkeys(kinds):
+            if kind.startswith("inplace") and sweeps % 2:
+                continue
+            t, u, lay, bpf = run_form(flags, geom, a, storage, kind, sweeps)
+            l2, mx = rel_errors(u, u_ref)
+            r = {"mflups": round(u.shape[1] / t / 1e6, 1), "speedup_vs_f64": round(t_ref / t, 3),
+                 "hbm_frac": round(bpf * u.shape[1] / t / 1e9 / HBM_PEAK_GBS, 4),
+                 "bytes_per_flup": round(bpf, 2), "u_rel_l2": float(f"{l2:.3e}"),
+                 "u_rel_max": float(f"{mx:.3e}"),
+                 "layout": {"stride": lay.stride, "nontemporal": lay.nontemporal,
+                            "xcd_chunk": lay.xcd_chunk}}
+            rec[kind] = r
+            del u
+            torch.cuda.empty_cache()
+        best = max(rec, key=lambda k: rec[k]["mflups"])
+        forms[storage] = dict(rec[best], sweep=best,
+                              **{f"mflups_{k}": rec[k]["mflups"] for k in rec if k != best})
+        print(f"precision {storage}: {forms[storage]}", file=sys.stderr, flush=True)
+    return forms
+
+
+def crop_vs_oracle(crop, geom, a, sweeps):
+    """Every storage form on the oracle's crop: velocity error vs the oracle."""
+    import torch
+    import oracle as O
+    flags_np, sp, f_orc, prm = crop
+    _, u_orc, _ = O.moments(prm, sp.adj, f_orc)
+    u_orc = torch.from_numpy(np.ascontiguousarray(u_orc)).cuda()
+    flags = torch.from_numpy(flags_np).cuda()
+    from paper_1111_1129_amd.tune import Layout
+    out = {}
+    for storage in ("f64", "f64s", "f32", "f32s", "f16s"):
+        _, u, _, _ = run_form(flags, geom, a, storage, a.sweep, sweeps, Layout(None, False, 0))
+        l2, mx = rel_errors(u, u_orc)
+        out[storage] = {"u_rel_l2": float(f"{l2:.3e}"), "u_rel_max": float(f"{mx:.3e}")}
+    return out
 
 
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only (one MI355X); "
+                                   "--gpus must be 1"}))
         sys.exit(2)
     import torch
     from paper_1111_1129_amd import _native as N
@@ -212,8 +339,11 @@ def main():
         import bench_experiments
         getattr(bench_experiments, a.experiment)(a)
         return
+    if not a.sweeps:
+        a.sweeps = 500 if a.workload == "large_packing" else 1000
     dev = torch.device("cuda:0")
-    geom, desc = make_workload(a.workload)
+    geom, desc = make_workload(a.workload, a.scale)
+    print(f"workload {a.workload}: {geom.n_fluid} fluid cells", file=sys.stderr, flush=True)
     flags = torch.from_numpy(np.ascontiguousarray(geom.flags)).to(dev)
     lay = None
     if a.sweep == "auto":
@@ -239,7 +369,7 @@ def main():
         stride, nt, chunk = None, False, 0
     prm = L.params(0.8, 3.0 / 16.0, (1e-6, 0.0, 0.0), a.storage, nontemporal=nt, xcd_chunk=chunk)
     stream = torch.cuda.current_stream()
-    from paper_1111_1129_amd.tune import Sweeper
+    from paper_1111_1129_amd.tune import Layout, Sweeper
     if a.sweep.startswith("inplace") and a.sweeps % 2:
         print(json.dumps({"error": "the in-place sweep needs an even --sweeps"}))
         sys.exit(2)
@@ -254,17 +384,20 @@ def main():
         if ev is not None:
             ev[1].record(stream)
         _, _, totals = L.moments(st, fields=False)
-        return lat, sw, totals
+        return lat, sw, st, totals
 
-    for _ in range(a.warmup):
+    for k in range(a.warmup):
         one_pass()
+        print(f"warmup pass {k + 1}/{a.warmup} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(a.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(a.steps):
-        lat, sw, totals = one_pass(events[k])
+        lat, sw, st, totals = one_pass(events[k])
+        if (k + 1) % 5 == 0 or k + 1 == a.steps:
+            print(f"timed pass {k + 1}/{a.steps} queued", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     n_fluid = lat.n_fluid
@@ -309,9 +442,29 @@ def main():
                      "avg_launch_us": round(launch_s * 1e6, 2)},
         "cpu_baseline": None,
     }
+    if a.precision and a.storage == "f64":
+        # reference velocity of the FP64 run (the last timed pass's state)
+        _, u_ref, _ = L.moments(st)
+        del lat, sw, st
+        torch.cuda.empty_cache()
+        forms = precision_leg(flags, geom, a, a.sweeps, u_ref, launch_s)
+        line["precision"] = {
+            "reference": f"the FP64 run ({a.sweep} sweep, {a.sweeps} sweeps from rest, g_x = 1e-6) "
+                         "stands in for the oracle at this size; its sweep is parity-checked "
+                         "against the oracle (1e-12) on the tube, the crop and sampled ranges of "
+                         "this workload",
+            "f64": {"mflups": round(n_fluid / launch_s / 1e6, 1), "sweep": a.sweep,
+                    "hbm_frac": round(achieved / HBM_PEAK_GBS, 4)},
+            **forms}
+        del u_ref
+        torch.cuda.empty_cache()
     if a.cpu_seconds > 0:
-        line["cpu_baseline"] = cpu_baseline(geom, a.order, a.param, a.storage, a.cpu_seconds,
-                                            n_fluid)
+        crop_div = 4 if a.workload == "large_packing" else 1
+        base, crop = cpu_baseline(geom, a.order, a.param, a.storage, a.cpu_seconds, crop_div,
+                                  a.sweeps if crop_div > 1 else 0)
+        line["cpu_baseline"] = base
+        if crop is not None and "precision" in line:
+            line["precision"]["vs_oracle_on_crop"] = crop_vs_oracle(crop, geom, a, a.sweeps)
     print(json.dumps(line), flush=True)
 
 

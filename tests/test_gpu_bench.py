@@ -47,3 +47,30 @@ def test_bench_sweep_auto_picks_a_kind():
     assert d["config"]["sweep"] in SWEEPS
     assert "sweep kinds (MFLUPS)" in res.stderr
     assert d["cpu_baseline"] is None
+
+
+def test_bench_precision_and_crop_baseline():
+    """The headline path of the precision workload (edges / 8): the line
+    carries every storage form's speed-up and velocity error vs FP64, the
+    oracle's rate on the central crop, and every form's error against the
+    oracle on that crop."""
+    cmd = [sys.executable, os.path.join(ROOT, "bench.py"), "--workload", "large_packing",
+           "--scale", "8", "--layout", "aligned", "--steps", "1", "--warmup", "1",
+           "--sweeps", "40"]
+    print("CASE bench precision", flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True, timeout=300)
+    assert res.returncode == 0, res.stderr[-2000:]
+    d = json.loads(res.stdout.strip().splitlines()[-1])
+    assert d["dtype"] == "f64" and d["config"]["workload"].startswith("large_packing")
+    p = d["precision"]
+    for st in ("f64s", "f32", "f32s", "f16s"):
+        for key in ("mflups", "speedup_vs_f64", "u_rel_l2", "u_rel_max", "sweep"):
+            assert key in p[st], (st, key)
+        assert p[st]["mflups"] > 0 and 0 <= p[st]["u_rel_l2"] < 1
+    assert p["f64s"]["u_rel_l2"] < 1e-9          # same arithmetic type, other rounding
+    assert p["f32s"]["u_rel_l2"] < p["f32"]["u_rel_l2"]  # the shift keeps FP32 accurate
+    crop = p["vs_oracle_on_crop"]
+    assert set(crop) == {"f64", "f64s", "f32", "f32s", "f16s"}
+    assert crop["f64"]["u_rel_l2"] < 1e-10 and crop["f64s"]["u_rel_l2"] < 1e-10
+    c = d["cpu_baseline"]
+    assert c["kind"] == "oracle" and "crop" in c["sample"] and c["value"] > 0

@@ -234,7 +234,8 @@ def sampled_step_vs_oracle(lat, sp, prm, st, advance, ranges, seed):
     seeded random values; both sides take their inputs from that one table,
     and the oracle steps the sampled cells through an identity adjacency."""
     S = lat.stride
-    cells = np.concatenate([np.arange(a, b) for a, b in ranges]).astype(np.int64)
+    # distinct cells (ranges may overlap): every slot then belongs to one cell
+    cells = np.unique(np.concatenate([np.arange(a, b) for a, b in ranges])).astype(np.int64)
     k = cells.size
     slots = np.empty((19, k), dtype=np.int64)
     slots[0] = cells                                   # rest population: own slot of row 0
@@ -284,6 +285,29 @@ def test_full_size_tube_sampled_step(sweep, stride, chunk):
     assert abs(float(st.f[:, :n].sum()) - mass0) <= 1e-12 * mass0
 
 
+def test_full_size_tube_whole_state_10_sweeps():
+    """The full 256^3 tube (7,797,209 cells) in the tuned launch configuration
+    of its sweep over 8-bit codes (row stride 2^23 + 8192, nontemporal
+    stores, XCD chunk 4): 10 FP64 sweeps from a seeded random state, every
+    one of the 19 x 7,797,209 PDFs within 1e-12 of the oracle."""
+    g = I.packing_tube(2)
+    lat = L.build(dev_flags(g), g.periodic, "lex", stride=8396800)
+    sp = O.build(g.flags, g.periodic, "lex", stride=lat.stride)
+    n = lat.n_fluid
+    assert n == sp.n_fluid == 7797209
+    print_case("tube whole state", n)
+    comp = L.narrow(L.compress(lat))
+    prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), "f64", nontemporal=True, xcd_chunk=4)
+    f0 = random_state(n, 31, stride=lat.stride)
+    st = L.init(lat, prm)
+    st.f.copy_(torch.from_numpy(f0))
+    L.step_c8(st, comp, 10)
+    got = st.f.cpu().numpy()
+    del st
+    orc = orun(prm, sp, f0, 10)
+    assert rel_err_f64(cells(got, n), cells(orc, n)) <= TOL_F64
+
+
 @pytest.fixture(scope="module")
 def large():
     """The 512x512x1024 packing (107 M cells) on the GPU and its oracle
@@ -299,6 +323,22 @@ def large():
     torch.cuda.empty_cache()
 
 
+def special_ranges(lat, comp):
+    """Cell ranges that a sample of the large packing must cover besides its
+    head, middle and tail: a tile read through 16-bit codes (not narrow), and
+    a row next to the y = 0 wall in the middle plane (bounce-back from the
+    wall layer; the head and tail planes lie next to the z walls)."""
+    rec = comp.tile_records.cpu().numpy()
+    wide = np.flatnonzero((rec[:, 19] == 0) & (rec[:, 18] == 0))
+    assert wide.size > 0
+    t = int(wide[wide.size // 2])
+    nx, ny, nz = lat.dims
+    index_of = lat.index_of.cpu().numpy()
+    row = index_of[nx * (1 + ny * (nz // 2)):nx * (2 + ny * (nz // 2))]
+    first = int(row[row >= 0].min())
+    return [(t * 256, min(t * 256 + 256, lat.n_fluid)), (first, first + 512)]
+
+
 def test_large_packing_full_size_sampled_step(large):
     """The 512x512x1024 packing (107 M cells) at full size: one GPU step over
     8-bit codes (16-bit in the tiles that need them) from a seeded state,
@@ -309,7 +349,7 @@ def test_large_packing_full_size_sampled_step(large):
     print_case("large packing full size", n)
     prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), "f64", nontemporal=True, xcd_chunk=64)
     st = L.init(lat, prm)
-    ranges = [(0, 4096), (n // 2, n // 2 + 4096), (n - 3001, n)]
+    ranges = [(0, 4096), (n // 2, n // 2 + 4096), (n - 3001, n)] + special_ranges(lat, comp)
     err = sampled_step_vs_oracle(lat, sp, prm, st, lambda: L.step_c8(st, comp, 1), ranges, 11)
     assert err <= TOL_F64
     del st
@@ -328,8 +368,8 @@ def test_large_packing_full_size_sampled_step_reduced(large, storage):
     prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), storage, nontemporal=True, xcd_chunk=1)
     st = L.init(lat, prm)
     dt = np.float16 if storage == "f16s" else np.float32
-    ranges = [(0, 4096), (n // 3, n // 3 + 3000), (n - 2049, n)]
-    cells_ = np.concatenate([np.arange(a, b) for a, b in ranges]).astype(np.int64)
+    ranges = [(0, 4096), (n // 3, n // 3 + 3000), (n - 2049, n)] + special_ranges(lat, comp)
+    cells_ = np.unique(np.concatenate([np.arange(a, b) for a, b in ranges])).astype(np.int64)
     k = cells_.size
     slots = np.empty((19, k), dtype=np.int64)
     slots[0] = cells_
