@@ -51,7 +51,8 @@ typedef enum {
     LBM_EOVERFLOW = -3,  /* index does not fit: 19*stride >= 2^32 or box >= 2^31 cells */
     LBM_EWORKSPACE = -4, /* workspace missing or smaller than the size query returned */
     LBM_EHIP = -5,       /* the HIP runtime reported an error */
-    LBM_EBARRIER = -6    /* persistent launch: a grid barrier exceeded its spin limit */
+    LBM_EBARRIER = -6,   /* persistent launch: a grid barrier exceeded its spin limit */
+    LBM_ENONFINITE = -7  /* lbm_moments with LBM_FLAG_CHECK_FINITE: a total is NaN or infinite */
 } lbm_status;
 
 /* Numbering schemes (Sec. 3 "Numbering scheme"; Sec. 7 blocking factor and
@@ -88,6 +89,9 @@ typedef enum {
 
 enum {
     LBM_FLAG_NONTEMPORAL = 1, /* write the new PDFs with nontemporal stores (Sec. 7) */
+    LBM_FLAG_CHECK_FINITE = 2, /* lbm_moments: read the totals back (synchronising the
+                                  stream) and return LBM_ENONFINITE if one is NaN or
+                                  infinite (a diverged run); ignored by the sweeps */
     /* Workgroup-to-XCD mapping of the sweep, bits [8, 16) of flags, a power of
      * two k: the hardware hands workgroup w to XCD w % 8; the sweep relabels
      * workgroups so that each XCD takes k consecutive list tiles before the
@@ -114,11 +118,15 @@ typedef struct {
     int32_t flags;   /* LBM_FLAG_* */
 } lbm_params;
 
-/* One geometry of a batch: list columns [base, base + n). */
+/* One geometry of a batch: list columns [base, base + n), run with parameter
+ * set params[param_index] of the call.  Segments are listed in increasing
+ * order and do not overlap.  When any segment of a call names a set other than
+ * 0, every non-empty segment must start on a multiple of 256 (a sweep tile),
+ * so that no tile holds cells of two segments. */
 typedef struct {
     int64_t base;
     int64_t n;
-    int32_t param_index; /* reserved: must be 0 (all segments share params[0]) */
+    int32_t param_index;
     int32_t pad;
 } lbm_segment;
 
@@ -163,15 +171,20 @@ lbm_status lbm_build_adjacency(const lbm_geom* g, const uint8_t* flag, int64_t b
                                size_t* ws_bytes, void* stream);
 
 /*
- * lbm_init -- equilibrium initial state.
+ * lbm_init -- equilibrium initial state (the configurations start from rest:
+ * rho = 1, u = 0; the TRT equilibrium is that of the sweep below, and the
+ * paper's FLUP count (Sec. 7) starts from such a state).
  *
  * Writes f_i = w_i [rho0 + 3 c_i.u0 + 9/2 (c_i.u0)^2 - 3/2 |u0|^2] (minus w_i in
  * shifted storage, computed as w_i [(rho0 - 1) + ...]) for list cells [0, n)
  * of every row.  The element type of f follows p->storage.  To initialise a
  * batch member, offset f by its base (in elements).
  *  p      (host) parameters (storage is used).
- *  u0     (host) 3 doubles, or NULL for u0 = 0.
- * Errors: LBM_EINVAL (NULL p/f, n < 0, stride < n, bad storage).
+ *  n, stride  cells written and row stride of f ([19][stride]).
+ *  f      PDF array, written (caller-owned).
+ *  rho0   density; u0 (host) 3 doubles, or NULL for u0 = 0.
+ * Errors: LBM_EINVAL (NULL p/f, n < 0, stride < n, bad storage, non-finite
+ * rho0), LBM_EOVERFLOW (19*stride >= 2^32), LBM_EHIP.
  */
 lbm_status lbm_init(const lbm_params* p, int64_t n, int64_t stride, void* f, double rho0,
                     const double* u0, void* stream);
@@ -179,7 +192,8 @@ lbm_status lbm_init(const lbm_params* p, int64_t n, int64_t stride, void* f, dou
 /*
  * lbm_step -- n_steps D3Q19 TRT pull sweeps over list cells [0, n)
  * (Sec. 1, Sec. 2, Sec. 7: TRT on D3Q19, structure of arrays, pull scheme,
- * indirect addressing, optionally nontemporal stores).
+ * indirect addressing, optionally nontemporal stores; a batch of geometries
+ * in one list is the paper's list of fluid cells holding several domains).
  *
  * Per cell m: gather g_0 = f[m], g_i = f[adj[i-1][m]]; rho = sum g;
  * j = sum c_i g_i; e+_i = w_i (rho + 9/2 (c_i.j)^2 - 3/2 |j|^2); e-_i = 3 w_i c_i.j;
@@ -188,23 +202,36 @@ lbm_status lbm_init(const lbm_params* p, int64_t n, int64_t stride, void* f, dou
  * store out_i at element i*stride + m of the destination array.  In shifted
  * storage the same map acts on f - w with rho read as the density deviation.
  *
- *  p, n_params  (host) parameters; n_params must be 1.
+ *  p, n_params  (host) n_params >= 1 parameter sets.  All sets share one
+ *               storage type and one set of launch flags (those of p[0]).
  *  seg, n_seg   (host) batch layout, or NULL/0 for one geometry [0, n).  Segments
- *               must lie inside [0, n) and not overlap.  They do not change the
- *               sweep (adjacency entries already carry each member's base).
+ *               lie inside [0, n), in increasing order, without overlap
+ *               (adjacency entries already carry each member's base).  Segment k
+ *               runs with p[seg[k].param_index]; cells outside every segment
+ *               with p[0].
  *  adj          uint32 [18][stride] from lbm_build_adjacency.
  *  ns           double [stride] solid fraction per list cell, or NULL (plain TRT).
  *  f_a, f_b     two PDF arrays [19][stride] of the storage type.  Step k reads the
  *               array written by step k-1 (f_a first): the result is in f_b if
  *               n_steps is odd, in f_a if even.
  *  persistent   0: one kernel launch per step.  1: a single cooperative launch
- *               runs all n_steps with a grid-wide barrier between steps; needs
- *               the workspace (query with workspace == NULL and ws_bytes != NULL).
- *  workspace, ws_bytes  see above; unused when persistent == 0 (may be NULL/0).
- * Errors: LBM_EINVAL (NULL p/adj/f_a/f_b, n < 0, stride < n, n_params != 1,
- * bad storage, tau_plus <= 1/2, bad segments, non-finite parameters),
- * LBM_EOVERFLOW (19*stride >= 2^32), LBM_EWORKSPACE, LBM_EHIP, LBM_EBARRIER
- * (persistent only; synchronous check after the launch).
+ *               runs all n_steps with a grid-wide barrier between steps (one
+ *               workgroup per CU) and synchronises the stream to report
+ *               LBM_EBARRIER.
+ *  workspace, ws_bytes  device scratch for the persistent launch (a barrier
+ *               block) and for per-segment parameter sets (a table of the sets
+ *               and one int32 per 256-cell tile).  A call that needs it and gets
+ *               workspace == NULL stores the size in *ws_bytes and does nothing
+ *               else (size query); a call with one parameter set and
+ *               persistent == 0 needs none (workspace may be NULL).
+ * Every member's state is bitwise what a run of that member alone (same
+ * parameters) gives, in either launch form.
+ * Errors: LBM_EINVAL (NULL p/adj/f_a/f_b, f_a == f_b, n < 0, stride < n,
+ * n_params < 1, sets differing in storage or flags, bad storage, tau_plus <= 1/2,
+ * non-finite parameters, bad segments: out of order, overlapping, outside
+ * [0, n), param_index outside [0, n_params), a segment not starting on a tile
+ * while sets differ), LBM_EOVERFLOW (19*stride >= 2^32), LBM_EWORKSPACE,
+ * LBM_EHIP, LBM_EBARRIER (persistent only; synchronous check after the launch).
  */
 lbm_status lbm_step(const lbm_params* p, int32_t n_params, const lbm_segment* seg, int32_t n_seg,
                     int64_t n, int64_t stride, const uint32_t* adj, const double* ns,
@@ -212,7 +239,32 @@ lbm_status lbm_step(const lbm_params* p, int32_t n_params, const lbm_segment* se
                     void* workspace, size_t* ws_bytes, void* stream);
 
 /*
- * lbm_step_adjoint -- transposed Jacobian of one lbm_step (FP64 storage only).
+ * lbm_step_batch -- lbm_step (same arguments, same results bit for bit) that
+ * reads the adjacency codes of lbm_compress_adjacency / lbm_narrow_codes
+ * instead of adj where a tile allows it, in either launch form: the byte
+ * reduction of lbm_step_c8 for a batch of geometries with per-segment
+ * parameter sets, and in the single persistent launch.
+ *
+ *  codes8   int8 [18][stride] from lbm_narrow_codes, or NULL (no 8-bit codes).
+ *  codes, tile_records  from lbm_compress_adjacency for the same n, stride and
+ *           adj, or both NULL (full list; codes8 must then be NULL too).
+ *  The other arguments as lbm_step.
+ * Errors: as lbm_step, and LBM_EINVAL for codes8 without codes or only one of
+ * codes and tile_records.
+ */
+lbm_status lbm_step_batch(const lbm_params* p, int32_t n_params, const lbm_segment* seg,
+                          int32_t n_seg, int64_t n, int64_t stride, const int8_t* codes8,
+                          const int16_t* codes, const int32_t* tile_records, const uint32_t* adj,
+                          const double* ns, void* f_a, void* f_b, int32_t n_steps,
+                          int32_t persistent, void* workspace, size_t* ws_bytes, void* stream);
+
+/*
+ * lbm_step_adjoint -- transposed Jacobian of one lbm_step (FP64 storage only):
+ * the reverse-mode derivative of the sweep of Sec. 7 that gives the gradient
+ * of the permeability (mean flux, proportional to the mean x velocity) with
+ * respect to a per-cell partial-bounce-back solid fraction.  The paper has no
+ * adjoint; the step is the exact transpose of the forward map written above
+ * (derived by hand from it), applied in reverse over checkpointed states.
  *
  * Forward: f^{t+1} = step(f^t; ns).  Given lam_next = lambda^{t+1} it writes
  * lambda^t = (d f^{t+1} / d f^t)^T lambda^{t+1} -- the local transposed
@@ -222,9 +274,11 @@ lbm_status lbm_step(const lbm_params* p, int32_t n_params, const lbm_segment* se
  * (g_opp(i) - f*_i), the derivative through the solid fraction.
  * With lam_next == NULL it writes the seed lambda^T = dJ/df^T of the
  * objective J = (1/n) sum_m (j_x(m) + G_x/2) (mean x velocity of the state
- * after the last step, i.e. the mean flux that sets the permeability); then
- * grad_ns is not touched.
+ * after the last step, i.e. the mean flux that sets the permeability; the
+ * value lbm_objective returns); then grad_ns is not touched.
  *
+ *  p        (host) parameters of the forward step (storage F64 or F64_SHIFTED).
+ *  n, stride, adj  as lbm_step.
  *  f_t      state entering step t ([19][stride], F64 or F64_SHIFTED).
  *  ns       solid fraction [stride] or NULL (then grad_ns is ignored).
  *  lam_next double [19][stride] or NULL; lam_t double [19][stride] (output).
@@ -257,25 +311,52 @@ lbm_status lbm_step_adjoint_c16(const lbm_params* p, int64_t n, int64_t stride,
                                 void* stream);
 
 /*
- * lbm_moments -- macroscopic fields and FP64 totals of a stored state.
+ * lbm_moments -- macroscopic fields and FP64 totals of a stored state (the
+ * density and velocity of each fluid cell, from the populations the next pull
+ * sweep of Sec. 7 gathers; the totals are what the mass-conservation and
+ * flux checks and the precision comparison read).
  *
  * Per list cell, from the populations it gathers through adj (the values the
  * next sweep would read): rho = sum g (1 + sum h in shifted storage),
- * u = j + G/2.  Totals per segment: {sum rho, sum u_x, sum u_y, sum u_z},
- * accumulated in FP64 double-double in a fixed order, so results do not
- * depend on timing.
+ * u = j + G/2 with the force G of the cell's segment.  Totals per segment:
+ * {sum rho, sum u_x, sum u_y, sum u_z}, accumulated in FP64 double-double in a
+ * fixed order, so results do not depend on timing.
  *
- *  rho   double [n] or NULL.   u  double [3][n] (rows x, y, z) or NULL.
+ *  p, n_params  (host) parameter sets as in lbm_step (the force and storage
+ *        are used); segment k reads p[seg[k].param_index].
+ *  n, stride, adj, f  the state (layout of lbm_step, storage p[0].storage).
+ *  rho   double [n] or NULL.   u  double [3][n] (rows x, y, z) or NULL.  Only
+ *        the cells of the segments are written.
  *  seg, n_seg  (host) segments, or NULL/0 for one segment [0, n).
  *  totals double [4 * max(n_seg,1)] or NULL.
  *  workspace, ws_bytes  scratch for the reduction (query with workspace NULL);
  *        not needed when totals == NULL.
+ *  With LBM_FLAG_CHECK_FINITE in p[0].flags and totals given, the call waits
+ *  for the totals and returns LBM_ENONFINITE if any of them is NaN or
+ *  infinite (the fields are written either way).
+ * Errors: LBM_EINVAL, LBM_EOVERFLOW, LBM_EWORKSPACE, LBM_EHIP, LBM_ENONFINITE.
+ */
+lbm_status lbm_moments(const lbm_params* p, int32_t n_params, int64_t n, int64_t stride,
+                       const uint32_t* adj, const void* f, double* rho, double* u,
+                       const lbm_segment* seg, int32_t n_seg, double* totals, void* workspace,
+                       size_t* ws_bytes, void* stream);
+
+/*
+ * lbm_objective -- the objective the adjoint differentiates: per segment the
+ * mean x velocity J = (1/N) sum_m (j_x(m) + G_x/2) over its N cells, the mean
+ * flux that sets the permeability k = nu J / G_x (nu = (tau+ - 1/2)/3).  The
+ * sum is lbm_moments' FP64 double-double total, divided by N on the device,
+ * so J equals totals[1] / N of lbm_moments bit for bit.
+ *
+ *  p, n_params, n, stride, adj, f, seg, n_seg  as lbm_moments.
+ *  J     double [max(n_seg, 1)] (output; an empty segment gives NaN).
+ *  workspace, ws_bytes  as lbm_moments with totals (query with workspace NULL).
  * Errors: LBM_EINVAL, LBM_EOVERFLOW, LBM_EWORKSPACE, LBM_EHIP.
  */
-lbm_status lbm_moments(const lbm_params* p, int64_t n, int64_t stride, const uint32_t* adj,
-                       const void* f, double* rho, double* u, const lbm_segment* seg,
-                       int32_t n_seg, double* totals, void* workspace, size_t* ws_bytes,
-                       void* stream);
+lbm_status lbm_objective(const lbm_params* p, int32_t n_params, int64_t n, int64_t stride,
+                         const uint32_t* adj, const void* f, const lbm_segment* seg,
+                         int32_t n_seg, double* J, void* workspace, size_t* ws_bytes,
+                         void* stream);
 
 /*
  * lbm_partition_stats -- communication metrics of cutting the list into

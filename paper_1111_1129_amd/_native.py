@@ -18,15 +18,18 @@ LIB_PATH = os.path.join(_PKG, "liblbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ECAPACITY, LBM_EOVERFLOW, LBM_EWORKSPACE, LBM_EHIP, LBM_EBARRIER = \
     0, -1, -2, -3, -4, -5, -6
+LBM_ENONFINITE = -7
 ORDERS = {"lex": 0, "blocked": 1, "morton1": 2, "morton2": 3, "random": 4, "hilbert": 5}
 STORAGES = {"f64": 0, "f64s": 1, "f32": 2, "f32s": 3, "f16s": 4}
 STORAGE_DTYPE = {0: torch.float64, 1: torch.float64, 2: torch.float32, 3: torch.float32,
                  4: torch.float16}
 FLAG_NONTEMPORAL = 1
+FLAG_CHECK_FINITE = 2
 FLAG_XCD_CHUNK_SHIFT = 8
+SEGMENT_ALIGN = 256  # segments with their own parameter sets start on a sweep tile
 
-ENTRY_POINTS = ("lbm_build_adjacency", "lbm_init", "lbm_step", "lbm_step_adjoint",
-                "lbm_moments", "lbm_partition_stats", "lbm_compress_adjacency", "lbm_step_c16",
+ENTRY_POINTS = ("lbm_build_adjacency", "lbm_init", "lbm_step", "lbm_step_batch",
+                "lbm_step_adjoint", "lbm_moments", "lbm_objective", "lbm_partition_stats", "lbm_compress_adjacency", "lbm_step_c16",
                 "lbm_step_inplace", "lbm_step_adjoint_c16", "lbm_narrow_codes", "lbm_step_c8",
                 "lbm_step_inplace_c8", "lbm_version", "lbm_status_string")
 
@@ -76,11 +79,17 @@ def load(path: str = LIB_PATH):
         lib.lbm_step.restype = I32
         lib.lbm_step.argtypes = [C.POINTER(lbm_params), I32, P, I32, I64, I64, P, P, P, P, I32,
                                  I32, P, C.POINTER(SZ), P]
+        lib.lbm_step_batch.restype = I32
+        lib.lbm_step_batch.argtypes = [C.POINTER(lbm_params), I32, P, I32, I64, I64, P, P, P, P,
+                                       P, P, P, I32, I32, P, C.POINTER(SZ), P]
+        lib.lbm_objective.restype = I32
+        lib.lbm_objective.argtypes = [C.POINTER(lbm_params), I32, I64, I64, P, P, P, I32, P, P,
+                                      C.POINTER(SZ), P]
         lib.lbm_step_adjoint.restype = I32
         lib.lbm_step_adjoint.argtypes = [C.POINTER(lbm_params), I64, I64, P, P, P, P, P, P, P]
         lib.lbm_moments.restype = I32
-        lib.lbm_moments.argtypes = [C.POINTER(lbm_params), I64, I64, P, P, P, P, P, I32, P, P,
-                                    C.POINTER(SZ), P]
+        lib.lbm_moments.argtypes = [C.POINTER(lbm_params), I32, I64, I64, P, P, P, P, P, I32, P,
+                                    P, C.POINTER(SZ), P]
         lib.lbm_partition_stats.restype = I32
         lib.lbm_partition_stats.argtypes = [I64, I64, P, I64, P, P, P, P, C.POINTER(SZ), P]
         lib.lbm_compress_adjacency.restype = I32
@@ -141,10 +150,21 @@ def make_params(tau_plus=0.8, magic=3.0 / 16.0, force=(0.0, 0.0, 0.0), storage="
 
 
 def make_segments(segs):
+    """ctypes array of segments from (base, n) or (base, n, param_index) tuples."""
     if not segs:
         return None, 0
-    arr = (lbm_segment * len(segs))(*[lbm_segment(int(b), int(n), 0, 0) for b, n in segs])
+    arr = (lbm_segment * len(segs))(*[lbm_segment(int(t[0]), int(t[1]),
+                                                  int(t[2]) if len(t) > 2 else 0, 0)
+                                      for t in segs])
     return arr, len(segs)
+
+
+def make_param_array(params):
+    """(pointer-compatible array, count) of one lbm_params or a list of them."""
+    if isinstance(params, lbm_params):
+        return params, 1
+    arr = (lbm_params * len(params))(*params)
+    return arr, len(params)
 
 
 # ---------------------------------------------------------------------------
@@ -172,14 +192,32 @@ def lbm_init(params: lbm_params, n, stride, f, rho0=1.0, u0=None, stream=None):
                         None if u is None else C.cast(u, C.c_void_p), _stream(stream))
 
 
-def lbm_step(params: lbm_params, n, stride, adj, ns, f_a, f_b, n_steps, persistent=0,
+def lbm_step(params, n, stride, adj, ns, f_a, f_b, n_steps, persistent=0,
              segments=None, workspace=None, ws_bytes=0, stream=None, query=False):
+    """params: one lbm_params or a list (parameter sets named by the segments'
+    third entry).  Returns (status, ws_bytes)."""
     lib = load()
     seg, n_seg = make_segments(segments)
+    prm, n_params = make_param_array(params)
     ws = C.c_size_t(ws_bytes)
-    st = lib.lbm_step(C.byref(params), 1, seg, n_seg, n, stride, _ptr(adj), _ptr(ns), _ptr(f_a),
-                      _ptr(f_b), n_steps, persistent, None if query else _ptr(workspace),
-                      C.byref(ws), _stream(stream))
+    st = lib.lbm_step(C.cast(C.pointer(prm), C.POINTER(lbm_params)), n_params, seg, n_seg, n,
+                      stride, _ptr(adj), _ptr(ns), _ptr(f_a), _ptr(f_b), n_steps, persistent,
+                      None if query else _ptr(workspace), C.byref(ws), _stream(stream))
+    return st, ws.value
+
+
+def lbm_step_batch(params, n, stride, codes8, codes, tile_records, adj, ns, f_a, f_b, n_steps,
+                   persistent=0, segments=None, workspace=None, ws_bytes=0, stream=None,
+                   query=False):
+    """lbm_step over the adjacency codes.  Returns (status, ws_bytes)."""
+    lib = load()
+    seg, n_seg = make_segments(segments)
+    prm, n_params = make_param_array(params)
+    ws = C.c_size_t(ws_bytes)
+    st = lib.lbm_step_batch(C.cast(C.pointer(prm), C.POINTER(lbm_params)), n_params, seg, n_seg,
+                            n, stride, _ptr(codes8), _ptr(codes), _ptr(tile_records), _ptr(adj),
+                            _ptr(ns), _ptr(f_a), _ptr(f_b), n_steps, persistent,
+                            None if query else _ptr(workspace), C.byref(ws), _stream(stream))
     return st, ws.value
 
 
@@ -190,14 +228,27 @@ def lbm_step_adjoint(params: lbm_params, n, stride, adj, f_t, ns, lam_next, lam_
                                 _ptr(lam_next), _ptr(lam_t), _ptr(grad_ns), _stream(stream))
 
 
-def lbm_moments(params: lbm_params, n, stride, adj, f, rho, u, segments, totals,
+def lbm_moments(params, n, stride, adj, f, rho, u, segments, totals,
                 workspace=None, ws_bytes=0, stream=None, query=False):
     lib = load()
     seg, n_seg = make_segments(segments)
+    prm, n_params = make_param_array(params)
     ws = C.c_size_t(ws_bytes)
-    st = lib.lbm_moments(C.byref(params), n, stride, _ptr(adj), _ptr(f), _ptr(rho), _ptr(u), seg,
-                         n_seg, _ptr(totals), None if query else _ptr(workspace), C.byref(ws),
-                         _stream(stream))
+    st = lib.lbm_moments(C.cast(C.pointer(prm), C.POINTER(lbm_params)), n_params, n, stride,
+                         _ptr(adj), _ptr(f), _ptr(rho), _ptr(u), seg, n_seg, _ptr(totals),
+                         None if query else _ptr(workspace), C.byref(ws), _stream(stream))
+    return st, ws.value
+
+
+def lbm_objective(params, n, stride, adj, f, segments, J, workspace=None, ws_bytes=0,
+                  stream=None, query=False):
+    lib = load()
+    seg, n_seg = make_segments(segments)
+    prm, n_params = make_param_array(params)
+    ws = C.c_size_t(ws_bytes)
+    st = lib.lbm_objective(C.cast(C.pointer(prm), C.POINTER(lbm_params)), n_params, n, stride,
+                           _ptr(adj), _ptr(f), seg, n_seg, _ptr(J),
+                           None if query else _ptr(workspace), C.byref(ws), _stream(stream))
     return st, ws.value
 
 

@@ -18,7 +18,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB_PATH = os.path.join(PKG, "liblbm.so")
-SOURCES = ["assembly.hip", "trt.hip", "persistent.hip", "moments.hip", "adjoint.hip",
+SOURCES = ["assembly.hip", "trt.hip", "batch.hip", "moments.hip", "adjoint.hip",
            "partition.hip", "compress.hip", "inplace.hip", "abi.cpp"]
 ARCH = "gfx950"
 

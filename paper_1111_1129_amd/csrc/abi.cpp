@@ -1,7 +1,7 @@
 // abi.cpp -- host-only entry points of the C ABI.
 #include "lbm.h"
 
-extern "C" int32_t lbm_version(void) { return 1 * 10000 + 0 * 100 + 0; }
+extern "C" int32_t lbm_version(void) { return 1 * 10000 + 1 * 100 + 0; }
 
 extern "C" const char* lbm_status_string(int32_t status) {
     switch (status) {
@@ -12,6 +12,7 @@ extern "C" const char* lbm_status_string(int32_t status) {
     case LBM_EWORKSPACE: return "workspace missing or too small";
     case LBM_EHIP: return "HIP runtime error";
     case LBM_EBARRIER: return "grid barrier timed out in persistent launch";
+    case LBM_ENONFINITE: return "non-finite totals (NaN or infinity in the state)";
     default: return "unknown status";
     }
 }

@@ -185,45 +185,6 @@ __global__ __launch_bounds__(kCTile) void k_narrow(const int16_t* __restrict__ c
     if (threadIdx.x == 0) rec[tile * kRec + Q] = narrow ? 1 : 0;
 }
 
-// One cell update of an escape-free tile, the slots rebuilt from the 16-bit
-// (CT = int16_t) or 8-bit (int8_t) codes in 32-bit arithmetic (every slot is
-// below 19 * stride < 2^32).  The per-tile part i * stride + tile * 256 + toff
-// is uniform (scalar); per lane it adds the lane and the code.
-template <int ST, bool PBB, bool NT, class CT>
-__device__ __forceinline__ void update_cell_coded(const typename Storage<ST>::T* __restrict__ src,
-                                                  typename Storage<ST>::T* __restrict__ dst,
-                                                  const CT* __restrict__ codes,
-                                                  const int32_t* __restrict__ rec,
-                                                  const double* __restrict__ ns, int64_t m,
-                                                  int64_t stride, const TrtConst& c) {
-    using T = typename Storage<ST>::T;
-    using A = typename Storage<ST>::A;
-    constexpr int32_t bounce = std::is_same_v<CT, int8_t> ? int32_t(kCode8Bounce)
-                                                          : int32_t(kCodeBounce);
-    int32_t cd[Q - 1];
-    const CT* cp = codes + m;
-#pragma unroll
-    for (int k = 0; k < Q - 1; ++k) cd[k] = ld_stream(cp + k * stride);
-    const uint32_t S = uint32_t(stride);
-    const uint32_t mm = uint32_t(m);
-    A g[Q];
-    g[0] = ld<T, A>(src + m);
-#pragma unroll
-    for (int k = 0; k < Q - 1; ++k) {
-        const uint32_t i = k + 1;
-        const uint32_t streamed = i * S + uint32_t(rec[k]) + mm + uint32_t(cd[k]);
-        const uint32_t bounced = uint32_t(opp(int(i))) * S + mm;
-        g[i] = ld<T, A>(src + (cd[k] == bounce ? bounced : streamed));
-    }
-    A sf = A(0);
-    if constexpr (PBB) sf = static_cast<A>(ns[m]);
-    A out[Q];
-    trt_collide<A, PBB>(g, out, c, sf);
-    T* dp = dst + m;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) st<T, A, NT>(dp + i * stride, out[i]);
-}
-
 template <int ST, bool PBB, bool NT>
 __global__ __launch_bounds__(kCTile) void k_trt_c16(const typename Storage<ST>::T* __restrict__ src,
                                                     typename Storage<ST>::T* __restrict__ dst,

@@ -31,7 +31,7 @@ inline bool valid_storage(int st) { return st >= LBM_F64 && st <= LBM_F16_SHIFTE
 // everything finite.
 inline bool valid_params(const lbm_params* p) {
     if (!p || !valid_storage(p->storage)) return false;
-    const int32_t known = LBM_FLAG_NONTEMPORAL | LBM_FLAG_XCD_CHUNK_MASK;
+    const int32_t known = LBM_FLAG_NONTEMPORAL | LBM_FLAG_CHECK_FINITE | LBM_FLAG_XCD_CHUNK_MASK;
     if (p->flags & ~known) return false;
     const int32_t chunk = (p->flags & LBM_FLAG_XCD_CHUNK_MASK) >> LBM_FLAG_XCD_CHUNK_SHIFT;
     if (chunk & (chunk - 1)) return false;  // a power of two (or 0)
@@ -53,13 +53,27 @@ inline lbm_status check_layout(int64_t n, int64_t stride) {
     return LBM_OK;
 }
 
-// Segments must be non-empty-or-empty ranges inside [0, n) that do not overlap.
-inline bool valid_segments(const lbm_segment* seg, int32_t n_seg, int64_t n) {
+// Segments are ranges inside [0, n) that do not overlap, listed in increasing
+// order, each naming a parameter set in [0, n_params).  When any segment
+// names a set other than 0, every non-empty segment starts on a tile of
+// kSegmentAlign cells, so no tile holds cells of two segments.
+constexpr int64_t kSegmentAlign = 256;
+
+inline bool uses_param_sets(const lbm_segment* seg, int32_t n_seg) {
+    for (int32_t k = 0; k < n_seg; ++k)
+        if (seg[k].param_index != 0) return true;
+    return false;
+}
+
+inline bool valid_segments(const lbm_segment* seg, int32_t n_seg, int64_t n, int32_t n_params) {
     if (n_seg < 0 || (n_seg > 0 && !seg)) return false;
+    const bool sets = uses_param_sets(seg, n_seg);
     int64_t prev_end = 0;
     for (int32_t s = 0; s < n_seg; ++s) {
-        if (seg[s].n < 0 || seg[s].base < prev_end || seg[s].base + seg[s].n > n) return false;
-        if (seg[s].param_index != 0) return false;
+        if (seg[s].n < 0 || seg[s].base < prev_end || seg[s].base > n || seg[s].n > n - seg[s].base)
+            return false;
+        if (seg[s].param_index < 0 || seg[s].param_index >= n_params) return false;
+        if (sets && seg[s].n > 0 && seg[s].base % kSegmentAlign != 0) return false;
         prev_end = seg[s].base + seg[s].n;
     }
     return true;

@@ -91,9 +91,12 @@ __global__ __launch_bounds__(kMomBlock) void k_moments(const typename Storage<ST
     }
 }
 
+// totals (4 values) and/or the objective (the x total divided by `count`)
 __global__ __launch_bounds__(kRedThreads) void k_reduce_partials(const double* __restrict__ partial,
                                                                  int64_t nblocks,
-                                                                 double* __restrict__ totals) {
+                                                                 double* __restrict__ totals,
+                                                                 double* __restrict__ objective,
+                                                                 double count) {
     __shared__ DD sh[kRedThreads][4];
     DD v[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
     // thread t sums blocks t, t + T, t + 2T, ... in order
@@ -103,66 +106,109 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_partials(const double* _
     }
     block_reduce4(v, sh);
     if (threadIdx.x == 0) {
+        if (totals) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) totals[q] = sh[0][q].hi + sh[0][q].lo;
+            for (int q = 0; q < 4; ++q) totals[q] = sh[0][q].hi + sh[0][q].lo;
+        }
+        if (objective) objective[0] = (sh[0][1].hi + sh[0][1].lo) / count;
     }
 }
 
 template <int ST>
-lbm_status launch_moments(const lbm_params& p, int64_t n, int64_t stride, const uint32_t* adj,
+lbm_status launch_moments(const lbm_params* p, int64_t n, int64_t stride, const uint32_t* adj,
                           const void* f, double* rho, double* u, const lbm_segment* seg,
-                          int32_t n_seg, double* totals, double* partial, hipStream_t s) {
+                          int32_t n_seg, double* totals, double* objective, double* partial,
+                          hipStream_t s) {
     lbm_segment whole{0, n, 0, 0};
     if (!seg || n_seg == 0) {
         seg = &whole;
         n_seg = 1;
     }
+    const bool reduce = totals || objective;
     for (int32_t k = 0; k < n_seg; ++k) {
         const int64_t cnt = seg[k].n;
+        const lbm_params& pk = p[seg[k].param_index];
         const int64_t blocks = std::max<int64_t>(1, (cnt + kMomBlock - 1) / kMomBlock);
         k_moments<ST><<<dim3(unsigned(blocks)), dim3(kMomBlock), 0, s>>>(
             static_cast<const typename Storage<ST>::T*>(f), adj, seg[k].base, cnt, stride,
-            p.force[0], p.force[1], p.force[2], rho, u, n, totals ? partial : nullptr);
+            pk.force[0], pk.force[1], pk.force[2], rho, u, n, reduce ? partial : nullptr);
         if (hipGetLastError() != hipSuccess) return LBM_EHIP;
-        if (totals) {
-            k_reduce_partials<<<1, kRedThreads, 0, s>>>(partial, blocks, totals + 4 * k);
+        if (reduce) {
+            k_reduce_partials<<<1, kRedThreads, 0, s>>>(partial, blocks, totals ? totals + 4 * k : nullptr,
+                                                        objective ? objective + k : nullptr,
+                                                        double(cnt));
             if (hipGetLastError() != hipSuccess) return LBM_EHIP;
         }
     }
     return LBM_OK;
 }
 
-}  // namespace lbm
-
-using namespace lbm;
-
-extern "C" lbm_status lbm_moments(const lbm_params* p, int64_t n, int64_t stride,
-                                  const uint32_t* adj, const void* f, double* rho, double* u,
-                                  const lbm_segment* seg, int32_t n_seg, double* totals,
-                                  void* workspace, size_t* ws_bytes, void* stream) {
-    if (!p || !valid_storage(p->storage)) return LBM_EINVAL;
+// Shared by lbm_moments and lbm_objective.
+lbm_status moments_call(const lbm_params* p, int32_t n_params, int64_t n, int64_t stride,
+                        const uint32_t* adj, const void* f, double* rho, double* u,
+                        const lbm_segment* seg, int32_t n_seg, double* totals, double* objective,
+                        void* workspace, size_t* ws_bytes, void* stream) {
+    if (!p || n_params < 1) return LBM_EINVAL;
     if (lbm_status st = check_layout(n, stride); st != LBM_OK) return st;
-    if (!valid_segments(seg, n_seg, n)) return LBM_EINVAL;
+    if (!valid_segments(seg, n_seg, n, n_params)) return LBM_EINVAL;
     int64_t largest = (seg && n_seg > 0) ? 0 : n;
     for (int32_t k = 0; seg && k < n_seg; ++k) largest = std::max(largest, seg[k].n);
-    const size_t need = totals ? align_up(size_t(std::max<int64_t>(1, (largest + kMomBlock - 1) / kMomBlock)) * 8 * sizeof(double), 256) : 0;
-    if (totals && !workspace) {
+    const bool reduce = totals || objective;
+    const size_t need = reduce ? align_up(size_t(std::max<int64_t>(1, (largest + kMomBlock - 1) / kMomBlock)) * 8 * sizeof(double), 256) : 0;
+    if (reduce && !workspace) {
         if (!ws_bytes) return LBM_EINVAL;
         *ws_bytes = need;
         return LBM_OK;
     }
-    if (totals && (!ws_bytes || *ws_bytes < need)) return LBM_EWORKSPACE;
+    if (reduce && (!ws_bytes || *ws_bytes < need)) return LBM_EWORKSPACE;
     if (!adj || !f) return LBM_EINVAL;
-    for (int d = 0; d < 3; ++d)
-        if (!std::isfinite(p->force[d])) return LBM_EINVAL;
+    for (int32_t k = 0; k < n_params; ++k) {
+        if (!valid_storage(p[k].storage) || p[k].storage != p[0].storage) return LBM_EINVAL;
+        for (int d = 0; d < 3; ++d)
+            if (!std::isfinite(p[k].force[d])) return LBM_EINVAL;
+    }
     hipStream_t s = as_stream(stream);
     double* partial = static_cast<double*>(workspace);
-    switch (p->storage) {
-    case LBM_F64: return launch_moments<LBM_F64>(*p, n, stride, adj, f, rho, u, seg, n_seg, totals, partial, s);
-    case LBM_F64_SHIFTED: return launch_moments<LBM_F64_SHIFTED>(*p, n, stride, adj, f, rho, u, seg, n_seg, totals, partial, s);
-    case LBM_F32: return launch_moments<LBM_F32>(*p, n, stride, adj, f, rho, u, seg, n_seg, totals, partial, s);
-    case LBM_F32_SHIFTED: return launch_moments<LBM_F32_SHIFTED>(*p, n, stride, adj, f, rho, u, seg, n_seg, totals, partial, s);
-    case LBM_F16_SHIFTED: return launch_moments<LBM_F16_SHIFTED>(*p, n, stride, adj, f, rho, u, seg, n_seg, totals, partial, s);
+    lbm_status st;
+    switch (p[0].storage) {
+    case LBM_F64: st = launch_moments<LBM_F64>(p, n, stride, adj, f, rho, u, seg, n_seg, totals, objective, partial, s); break;
+    case LBM_F64_SHIFTED: st = launch_moments<LBM_F64_SHIFTED>(p, n, stride, adj, f, rho, u, seg, n_seg, totals, objective, partial, s); break;
+    case LBM_F32: st = launch_moments<LBM_F32>(p, n, stride, adj, f, rho, u, seg, n_seg, totals, objective, partial, s); break;
+    case LBM_F32_SHIFTED: st = launch_moments<LBM_F32_SHIFTED>(p, n, stride, adj, f, rho, u, seg, n_seg, totals, objective, partial, s); break;
+    case LBM_F16_SHIFTED: st = launch_moments<LBM_F16_SHIFTED>(p, n, stride, adj, f, rho, u, seg, n_seg, totals, objective, partial, s); break;
     default: return LBM_EINVAL;
     }
+    if (st != LBM_OK || !totals || !(p[0].flags & LBM_FLAG_CHECK_FINITE)) return st;
+    // read the totals back in fixed-size pieces (no host allocation) and test them
+    const int64_t count = 4 * int64_t(std::max<int32_t>(n_seg, 1));
+    double buf[64];
+    bool finite = true;
+    for (int64_t i0 = 0; i0 < count; i0 += 64) {
+        const int64_t c = std::min<int64_t>(64, count - i0);
+        LBM_TRY_HIP(hipMemcpyAsync(buf, totals + i0, size_t(c) * sizeof(double), hipMemcpyDeviceToHost, s));
+        LBM_TRY_HIP(hipStreamSynchronize(s));
+        for (int64_t i = 0; i < c; ++i) finite = finite && std::isfinite(buf[i]);
+    }
+    return finite ? LBM_OK : LBM_ENONFINITE;
+}
+
+}  // namespace lbm
+
+using namespace lbm;
+
+extern "C" lbm_status lbm_moments(const lbm_params* p, int32_t n_params, int64_t n,
+                                  int64_t stride, const uint32_t* adj, const void* f, double* rho,
+                                  double* u, const lbm_segment* seg, int32_t n_seg, double* totals,
+                                  void* workspace, size_t* ws_bytes, void* stream) {
+    return moments_call(p, n_params, n, stride, adj, f, rho, u, seg, n_seg, totals, nullptr,
+                        workspace, ws_bytes, stream);
+}
+
+extern "C" lbm_status lbm_objective(const lbm_params* p, int32_t n_params, int64_t n,
+                                    int64_t stride, const uint32_t* adj, const void* f,
+                                    const lbm_segment* seg, int32_t n_seg, double* J,
+                                    void* workspace, size_t* ws_bytes, void* stream) {
+    if (!J) return LBM_EINVAL;
+    return moments_call(p, n_params, n, stride, adj, f, nullptr, nullptr, seg, n_seg, nullptr, J,
+                        workspace, ws_bytes, stream);
 }

@@ -24,11 +24,18 @@ namespace lbm {
 
 constexpr int kBlock = 256;
 
-// persistent.hip
-constexpr size_t kPersistentWs = 256;
-lbm_status launch_persistent(int storage, const TrtConst& c, bool nt, int chunk_shift, int64_t n,
-                             int64_t stride, const uint32_t* adj, const double* ns, void* fa,
-                             void* fb, int n_steps, void* ws, hipStream_t s);
+// batch.hip: sweeps with constants from a parameter table (per-segment
+// parameter sets, persistent launch)
+size_t step_batch_workspace(int32_t n_params, const lbm_segment* seg, int32_t n_seg, int64_t n);
+lbm_status step_batch(const lbm_params* p, int32_t n_params, const lbm_segment* seg,
+                      int32_t n_seg, int64_t n, int64_t stride, const int8_t* codes8,
+                      const int16_t* codes, const int32_t* tile_records, const uint32_t* adj,
+                      const double* ns, void* f_a, void* f_b, int32_t n_steps, bool persistent,
+                      void* workspace, hipStream_t s);
+// compress.hip: one launch per step over 16-bit / 8-bit codes
+lbm_status step_coded(const lbm_params& p, int64_t n, int64_t stride, const int8_t* codes8,
+                      const int16_t* codes, const int32_t* toff, const uint32_t* adj,
+                      const double* ns, void* fa, void* fb, int n_steps, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // init
@@ -99,12 +106,10 @@ lbm_status launch_steps(const TrtConst& c, int chunk_shift, int64_t n, int64_t s
 
 template <int ST>
 lbm_status dispatch_step(const lbm_params& p, int64_t n, int64_t stride, const uint32_t* adj,
-                         const double* ns, void* fa, void* fb, int n_steps, int persistent,
-                         void* ws, hipStream_t s) {
+                         const double* ns, void* fa, void* fb, int n_steps, hipStream_t s) {
     const TrtConst c = make_trt_const(p);
     const bool nt = (p.flags & LBM_FLAG_NONTEMPORAL) != 0;
     const int cs = chunk_shift_for(p.flags, n, kBlock);
-    if (persistent) return launch_persistent(ST, c, nt, cs, n, stride, adj, ns, fa, fb, n_steps, ws, s);
     if (ns) return nt ? launch_steps<ST, true, true>(c, cs, n, stride, adj, ns, fa, fb, n_steps, s)
                       : launch_steps<ST, true, false>(c, cs, n, stride, adj, ns, fa, fb, n_steps, s);
     return nt ? launch_steps<ST, false, true>(c, cs, n, stride, adj, ns, fa, fb, n_steps, s)
@@ -130,30 +135,53 @@ extern "C" lbm_status lbm_init(const lbm_params* p, int64_t n, int64_t stride, v
     }
 }
 
+extern "C" lbm_status lbm_step_batch(const lbm_params* p, int32_t n_params,
+                                     const lbm_segment* seg, int32_t n_seg, int64_t n,
+                                     int64_t stride, const int8_t* codes8, const int16_t* codes,
+                                     const int32_t* tile_records, const uint32_t* adj,
+                                     const double* ns, void* f_a, void* f_b, int32_t n_steps,
+                                     int32_t persistent, void* workspace, size_t* ws_bytes,
+                                     void* stream) {
+    if (!p || n_params < 1 || n_seg < 0 || (n_seg > 0 && !seg)) return LBM_EINVAL;
+    const bool table = persistent || uses_param_sets(seg, n_seg);
+    if (table && !workspace) {  // size query
+        if (!ws_bytes) return LBM_EINVAL;
+        *ws_bytes = step_batch_workspace(n_params, seg, n_seg, std::max<int64_t>(n, 0));
+        return LBM_OK;
+    }
+    for (int32_t k = 0; k < n_params; ++k) {
+        if (!valid_params(&p[k])) return LBM_EINVAL;
+        // one array type and one set of launch options for the whole launch
+        if (p[k].storage != p[0].storage || p[k].flags != p[0].flags) return LBM_EINVAL;
+    }
+    if (!adj || !f_a || !f_b || f_a == f_b || n_steps < 0) return LBM_EINVAL;
+    if ((codes8 && !codes) || ((codes != nullptr) != (tile_records != nullptr))) return LBM_EINVAL;
+    if (lbm_status st = check_layout(n, stride); st != LBM_OK) return st;
+    if (!valid_segments(seg, n_seg, n, n_params)) return LBM_EINVAL;
+    if (table && (!ws_bytes || *ws_bytes < step_batch_workspace(n_params, seg, n_seg, n)))
+        return LBM_EWORKSPACE;
+    if (n == 0 || n_steps == 0) return LBM_OK;
+    hipStream_t s = as_stream(stream);
+    if (table)
+        return step_batch(p, n_params, seg, n_seg, n, stride, codes8, codes, tile_records, adj, ns,
+                          f_a, f_b, n_steps, persistent != 0, workspace, s);
+    // one parameter set, one launch per step: constants as kernel arguments
+    if (codes) return step_coded(*p, n, stride, codes8, codes, tile_records, adj, ns, f_a, f_b, n_steps, s);
+    switch (p->storage) {
+    case LBM_F64: return dispatch_step<LBM_F64>(*p, n, stride, adj, ns, f_a, f_b, n_steps, s);
+    case LBM_F64_SHIFTED: return dispatch_step<LBM_F64_SHIFTED>(*p, n, stride, adj, ns, f_a, f_b, n_steps, s);
+    case LBM_F32: return dispatch_step<LBM_F32>(*p, n, stride, adj, ns, f_a, f_b, n_steps, s);
+    case LBM_F32_SHIFTED: return dispatch_step<LBM_F32_SHIFTED>(*p, n, stride, adj, ns, f_a, f_b, n_steps, s);
+    case LBM_F16_SHIFTED: return dispatch_step<LBM_F16_SHIFTED>(*p, n, stride, adj, ns, f_a, f_b, n_steps, s);
+    default: return LBM_EINVAL;
+    }
+}
+
 extern "C" lbm_status lbm_step(const lbm_params* p, int32_t n_params, const lbm_segment* seg,
                                int32_t n_seg, int64_t n, int64_t stride, const uint32_t* adj,
                                const double* ns, void* f_a, void* f_b, int32_t n_steps,
                                int32_t persistent, void* workspace, size_t* ws_bytes,
                                void* stream) {
-    if (persistent && !workspace) {
-        // size query
-        if (!ws_bytes) return LBM_EINVAL;
-        *ws_bytes = kPersistentWs;
-        return LBM_OK;
-    }
-    if (!valid_params(p) || n_params != 1 || !adj || !f_a || !f_b || n_steps < 0) return LBM_EINVAL;
-    if (f_a == f_b) return LBM_EINVAL;
-    if (lbm_status st = check_layout(n, stride); st != LBM_OK) return st;
-    if (!valid_segments(seg, n_seg, n)) return LBM_EINVAL;
-    if (persistent && (!ws_bytes || *ws_bytes < kPersistentWs)) return LBM_EWORKSPACE;
-    if (n == 0 || n_steps == 0) return LBM_OK;
-    hipStream_t s = as_stream(stream);
-    switch (p->storage) {
-    case LBM_F64: return dispatch_step<LBM_F64>(*p, n, stride, adj, ns, f_a, f_b, n_steps, persistent, workspace, s);
-    case LBM_F64_SHIFTED: return dispatch_step<LBM_F64_SHIFTED>(*p, n, stride, adj, ns, f_a, f_b, n_steps, persistent, workspace, s);
-    case LBM_F32: return dispatch_step<LBM_F32>(*p, n, stride, adj, ns, f_a, f_b, n_steps, persistent, workspace, s);
-    case LBM_F32_SHIFTED: return dispatch_step<LBM_F32_SHIFTED>(*p, n, stride, adj, ns, f_a, f_b, n_steps, persistent, workspace, s);
-    case LBM_F16_SHIFTED: return dispatch_step<LBM_F16_SHIFTED>(*p, n, stride, adj, ns, f_a, f_b, n_steps, persistent, workspace, s);
-    default: return LBM_EINVAL;
-    }
+    return lbm_step_batch(p, n_params, seg, n_seg, n, stride, nullptr, nullptr, nullptr, adj, ns,
+                          f_a, f_b, n_steps, persistent, workspace, ws_bytes, stream);
 }

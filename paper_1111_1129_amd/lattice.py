@@ -34,9 +34,9 @@ class Lattice:
     n_fluid: int
     base: int
     stride: int
-    index_of: torch.Tensor  # int32 [n_box], -1 = solid
-    cell_of: torch.Tensor   # int32 [n_fluid]
-    adj: torch.Tensor       # int32 storage of uint32 [18][stride]
+    index_of: torch.Tensor | None  # int32 [n_box], -1 = solid (None for a batch)
+    cell_of: torch.Tensor | None   # int32 [n_fluid] (None for a batch)
+    adj: torch.Tensor              # int32 storage of uint32 [18][stride]
 
     @property
     def device(self):
@@ -98,19 +98,25 @@ def build(flags: torch.Tensor, periodic: int = 0, order: str = "lex", param: int
 
 @dataclasses.dataclass
 class State:
-    """PDF ping-pong arrays [19][stride] and the TRT parameters."""
+    """PDF ping-pong arrays [19][stride] and the TRT parameters: one parameter
+    set, or a list of sets that the segments (base, n, set index) select."""
 
     lattice: Lattice
-    params: N.lbm_params
+    params: N.lbm_params | list
     f: torch.Tensor                 # current state
     g: torch.Tensor                 # the other array
     ns: torch.Tensor | None = None  # float64 [stride] solid fraction (PBB) or None
     n: int = 0                      # number of listed cells the sweep covers
     steps: int = 0
+    segments: list | None = None    # default segments of step() / moments()
+
+    @property
+    def first_params(self) -> N.lbm_params:
+        return self.params[0] if isinstance(self.params, list) else self.params
 
     @property
     def storage(self) -> int:
-        return self.params.storage
+        return self.first_params.storage
 
 
 def params(tau_plus=0.8, magic=3.0 / 16.0, force=(0.0, 0.0, 0.0), storage="f64",
@@ -122,19 +128,36 @@ def params(tau_plus=0.8, magic=3.0 / 16.0, force=(0.0, 0.0, 0.0), storage="f64",
     return N.make_params(tau_plus, magic, force, storage, flags)
 
 
-def init(lat: Lattice, prm: N.lbm_params, rho0: float = 1.0, u0=None, ns: torch.Tensor | None = None,
-         n: int | None = None, stream=None) -> State:
-    """Equilibrium state for the listed cells [0, n) (default: base + N_f)."""
+def init(lat: Lattice, prm, rho0: float = 1.0, u0=None, ns: torch.Tensor | None = None,
+         n: int | None = None, stream=None, segments=None) -> State:
+    """Equilibrium state for the listed cells [0, n) (default: base + N_f).
+    prm: one parameter set, or a list of sets (one storage type) that the
+    segments select."""
     n = lat.base + lat.n_fluid if n is None else n
-    dt = N.STORAGE_DTYPE[prm.storage]
+    first = prm[0] if isinstance(prm, list) else prm
+    dt = N.STORAGE_DTYPE[first.storage]
     # both arrays in one allocation: their relative placement is fixed
     pair = torch.empty((2, 19, lat.stride), dtype=dt, device=lat.device)
     f, g = pair[0], pair[1]
-    st = N.lbm_init(prm, n, lat.stride, f, rho0, u0, stream)
+    st = N.lbm_init(first, n, lat.stride, f, rho0, u0, stream)
     N._check("lbm_init", st)
     if ns is not None:
         assert ns.dtype == torch.float64 and ns.numel() >= n and ns.is_contiguous()
-    return State(lat, prm, f, g, ns, n, 0)
+    return State(lat, prm, f, g, ns, n, 0, segments)
+
+
+def _needs_workspace(persistent: bool, segments) -> bool:
+    """A persistent launch, or segments selecting parameter sets other than 0,
+    read a table / barrier block from the caller's workspace."""
+    return bool(persistent) or any(len(t) > 2 and t[2] != 0 for t in (segments or ()))
+
+
+def _step_workspace(state: State, persistent: bool, segments, query):
+    if not _needs_workspace(persistent, segments):
+        return None, 0
+    st, wsn = query()
+    N._check("lbm_step", st)
+    return torch.empty(max(wsn, 1), dtype=torch.uint8, device=state.lattice.device), wsn
 
 
 def set_state(state: State, f: torch.Tensor):
@@ -146,13 +169,10 @@ def step(state: State, n_steps: int = 1, persistent: bool = False, segments=None
     """Advance the state by n_steps sweeps (one launch per step, or one
     persistent cooperative launch)."""
     lat = state.lattice
-    ws = None
-    wsn = 0
-    if persistent:
-        st, wsn = N.lbm_step(state.params, state.n, lat.stride, lat.adj, state.ns, state.f, state.g,
-                             n_steps, 1, segments, query=True)
-        N._check("lbm_step", st)
-        ws = torch.empty(wsn, dtype=torch.uint8, device=lat.device)
+    segments = state.segments if segments is None else segments
+    ws, wsn = _step_workspace(state, persistent, segments, lambda: N.lbm_step(
+        state.params, state.n, lat.stride, lat.adj, state.ns, state.f, state.g, n_steps, 1,
+        segments, query=True))
     st, _ = N.lbm_step(state.params, state.n, lat.stride, lat.adj, state.ns, state.f, state.g,
                        n_steps, int(persistent), segments, ws, wsn, stream)
     N._check("lbm_step", st)
@@ -162,24 +182,59 @@ def step(state: State, n_steps: int = 1, persistent: bool = False, segments=None
     return state
 
 
-def moments(state: State, fields: bool = True, segments=None, stream=None):
-    """(rho [n], u [3][n], totals [n_seg or 1][4]) in FP64 on the device."""
+def moments(state: State, fields: bool = True, segments=None, stream=None,
+            check_finite: bool = False):
+    """(rho [n], u [3][n], totals [n_seg or 1][4]) in FP64 on the device.
+    check_finite: the library reads the totals back and raises LbmError
+    (LBM_ENONFINITE) if one is NaN or infinite."""
     assert getattr(state, "phase", 0) == 0, "in-place state must be in phase 0 (an even step count)"
     lat = state.lattice
+    segments = getattr(state, "segments", None) if segments is None else segments
+    params = state.params
+    if check_finite:
+        params = _with_flag(params, N.FLAG_CHECK_FINITE)
     n = state.n
     dev = lat.device
     rho = torch.empty(n, dtype=torch.float64, device=dev) if fields else None
     u = torch.empty((3, n), dtype=torch.float64, device=dev) if fields else None
     nseg = len(segments) if segments else 1
     totals = torch.empty((nseg, 4), dtype=torch.float64, device=dev)
-    st, wsn = N.lbm_moments(state.params, n, lat.stride, lat.adj, state.f, rho, u, segments,
+    st, wsn = N.lbm_moments(params, n, lat.stride, lat.adj, state.f, rho, u, segments,
                             totals, query=True)
     N._check("lbm_moments", st)
     ws = torch.empty(max(wsn, 1), dtype=torch.uint8, device=dev)
-    st, _ = N.lbm_moments(state.params, n, lat.stride, lat.adj, state.f, rho, u, segments, totals,
+    st, _ = N.lbm_moments(params, n, lat.stride, lat.adj, state.f, rho, u, segments, totals,
                           ws, wsn, stream)
     N._check("lbm_moments", st)
     return rho, u, totals
+
+
+def _with_flag(params, flag: int):
+    """Copies of the parameter set(s) with `flag` added to their flags."""
+    def one(p):
+        q = N.lbm_params.from_buffer_copy(p)
+        q.flags |= flag
+        return q
+    return [one(p) for p in params] if isinstance(params, list) else one(params)
+
+
+def objective(state: State, segments=None, stream=None) -> torch.Tensor:
+    """J [n_seg or 1] (FP64, device): per segment the mean x velocity
+    (j_x + G_x/2) over its cells, the mean flux whose gradient the adjoint
+    computes (lbm_objective)."""
+    assert getattr(state, "phase", 0) == 0, "in-place state must be in phase 0 (an even step count)"
+    lat = state.lattice
+    segments = getattr(state, "segments", None) if segments is None else segments
+    nseg = len(segments) if segments else 1
+    J = torch.empty(nseg, dtype=torch.float64, device=lat.device)
+    st, wsn = N.lbm_objective(state.params, state.n, lat.stride, lat.adj, state.f, segments, J,
+                              query=True)
+    N._check("lbm_objective", st)
+    ws = torch.empty(max(wsn, 1), dtype=torch.uint8, device=lat.device)
+    st, _ = N.lbm_objective(state.params, state.n, lat.stride, lat.adj, state.f, segments, J, ws,
+                            wsn, stream)
+    N._check("lbm_objective", st)
+    return J
 
 
 def partition_stats(lat: Lattice, n_chunks: int, n: int | None = None, stream=None):
@@ -247,32 +302,46 @@ def narrow(comp: Compressed, stream=None) -> Compressed:
     return comp
 
 
-def step_c8(state: State, comp: Compressed, n_steps: int = 1, stream=None):
+def _step_coded(state: State, comp: Compressed, codes8, n_steps, persistent, segments, stream):
+    lat = state.lattice
+    assert comp.n == state.n and comp.codes.shape[1] == lat.stride
+    segments = state.segments if segments is None else segments
+    if persistent or isinstance(state.params, list) or segments:
+        # lbm_step_batch: per-segment parameter sets and / or one persistent launch
+        ws, wsn = _step_workspace(state, persistent, segments, lambda: N.lbm_step_batch(
+            state.params, state.n, lat.stride, codes8, comp.codes, comp.tile_records, lat.adj,
+            state.ns, state.f, state.g, n_steps, 1, segments, query=True))
+        st, _ = N.lbm_step_batch(state.params, state.n, lat.stride, codes8, comp.codes,
+                                 comp.tile_records, lat.adj, state.ns, state.f, state.g, n_steps,
+                                 int(persistent), segments, ws, wsn, stream)
+        N._check("lbm_step_batch", st)
+    elif codes8 is not None:
+        st = N.lbm_step_c8(state.params, state.n, lat.stride, codes8, comp.codes,
+                           comp.tile_records, lat.adj, state.ns, state.f, state.g, n_steps, stream)
+        N._check("lbm_step_c8", st)
+    else:
+        st = N.lbm_step_c16(state.params, state.n, lat.stride, comp.codes, comp.tile_records,
+                            lat.adj, state.ns, state.f, state.g, n_steps, stream)
+        N._check("lbm_step_c16", st)
+    if n_steps % 2 == 1:
+        state.f, state.g = state.g, state.f
+    state.steps += n_steps
+    return state
+
+
+def step_c8(state: State, comp: Compressed, n_steps: int = 1, stream=None,
+            persistent: bool = False, segments=None):
     """As step(), reading 8-bit codes in narrow tiles and 16-bit codes
-    elsewhere (results bitwise equal)."""
-    lat = state.lattice
+    elsewhere (results bitwise equal); persistent / per-segment parameter
+    sets go through lbm_step_batch."""
     assert comp.codes8 is not None, "narrow(comp) first"
-    assert comp.n == state.n and comp.codes.shape[1] == lat.stride
-    st = N.lbm_step_c8(state.params, state.n, lat.stride, comp.codes8, comp.codes,
-                       comp.tile_records, lat.adj, state.ns, state.f, state.g, n_steps, stream)
-    N._check("lbm_step_c8", st)
-    if n_steps % 2 == 1:
-        state.f, state.g = state.g, state.f
-    state.steps += n_steps
-    return state
+    return _step_coded(state, comp, comp.codes8, n_steps, persistent, segments, stream)
 
 
-def step_c16(state: State, comp: Compressed, n_steps: int = 1, stream=None):
+def step_c16(state: State, comp: Compressed, n_steps: int = 1, stream=None,
+             persistent: bool = False, segments=None):
     """As step(), reading the 16-bit codes (results bitwise equal)."""
-    lat = state.lattice
-    assert comp.n == state.n and comp.codes.shape[1] == lat.stride
-    st = N.lbm_step_c16(state.params, state.n, lat.stride, comp.codes, comp.tile_records, lat.adj,
-                        state.ns, state.f, state.g, n_steps, stream)
-    N._check("lbm_step_c16", st)
-    if n_steps % 2 == 1:
-        state.f, state.g = state.g, state.f
-    state.steps += n_steps
-    return state
+    return _step_coded(state, comp, None, n_steps, persistent, segments, stream)
 
 
 class StepGraph:
@@ -372,16 +441,23 @@ class Batch:
     """Many geometries in one set of [19][S] / [18][S] arrays.
 
     Geometry k occupies columns [base_k, base_k + N_k); its adjacency entries
-    carry its base, so one sweep over [0, sum N_k) advances all of them.
+    carry its base, so one sweep over [0, total) advances all of them.  With
+    tile_align, every base is a multiple of 256 (the sweep tile), which lets
+    the members run with their own parameter sets (init with a list); the
+    columns between members are then padding that no segment claims.
     """
 
     def __init__(self, flags_list, periodic_list, order="lex", param=0, device="cuda",
-                 stride: int | None = None, counts=None):
+                 stride: int | None = None, counts=None, tile_align: bool = False):
         if counts is None:
             counts = [count_fluid(fl, per, order, param) for fl, per in zip(flags_list, periodic_list)]
         self.counts = list(counts)
-        self.bases = [sum(counts[:k]) for k in range(len(counts))]
-        self.total = sum(counts)
+        align = N.SEGMENT_ALIGN if tile_align else 1
+        self.bases, b = [], 0
+        for c in self.counts:
+            self.bases.append(b)
+            b = (b + c + align - 1) // align * align
+        self.total = self.bases[-1] + self.counts[-1] if self.counts else 0
         self.stride = aligned_stride(self.total) if stride is None else stride
         assert self.stride >= self.total
         self.adj = torch.zeros((18, self.stride), dtype=torch.int32, device=device)
@@ -391,8 +467,80 @@ class Batch:
                                        adj=self.adj))
         self.segments = list(zip(self.bases, self.counts))
         first = self.lattices[0]
+        # box <-> list maps are per member (self.lattices[k]); the batch has none
         self.lattice = Lattice(first.dims, first.periodic, order, param, self.total, 0,
-                               self.stride, first.index_of, first.cell_of, self.adj)
+                               self.stride, None, None, self.adj)
 
     def init(self, prm, rho0=1.0, u0=None, ns=None):
+        """State of the whole batch.  prm: one parameter set for every member,
+        or one per member (needs tile_align): member k then runs with prm[k]
+        and the state's segments name it."""
+        if isinstance(prm, list):
+            assert len(prm) == len(self.counts), "one parameter set per member"
+            assert all(b % N.SEGMENT_ALIGN == 0 for b in self.bases), "Batch(tile_align=True)"
+            segs = [(b, c, k) for k, (b, c) in enumerate(self.segments)]
+            return init(self.lattice, list(prm), rho0, u0, ns, n=self.total, segments=segs)
         return init(self.lattice, prm, rho0, u0, ns, n=self.total)
+
+
+# ---------------------------------------------------------------------------
+# checkpoint / restart
+# ---------------------------------------------------------------------------
+
+def _params_dict(p: N.lbm_params) -> dict:
+    return {"tau_plus": p.tau_plus, "magic": p.magic, "force": list(p.force),
+            "storage": p.storage, "flags": p.flags}
+
+
+def _params_from(d: dict) -> N.lbm_params:
+    return N.make_params(d["tau_plus"], d["magic"], d["force"], d["storage"], d["flags"])
+
+
+def checkpoint(state) -> dict:
+    """Host copy of what a restart needs: the geometry and ordering, the box
+    cell of every listed cell, the PDFs of the listed cells in list order
+    (post-collision values, the layout every sweep starts from), the
+    parameters, the solid fraction and the step count.  Plain tensors, ints,
+    floats and strings only, so torch.save / torch.load(weights_only=True)
+    round-trip it.  A state stepped in place must be in phase 0."""
+    assert getattr(state, "phase", 0) == 0, "in-place state must be in phase 0 (an even step count)"
+    lat = state.lattice
+    assert lat.cell_of is not None, "checkpoint one geometry (a batch member's own lattice)"
+    b, n = lat.base, lat.n_fluid
+    params = state.params if isinstance(state.params, list) else [state.params]
+    return {"dims": list(lat.dims), "periodic": int(lat.periodic), "order": lat.order,
+            "param": int(lat.param), "cell_of": lat.cell_of[:n].cpu(),
+            "f": state.f[:, b:b + n].cpu(), "params": [_params_dict(p) for p in params],
+            "ns": None if state.ns is None else state.ns[b:b + n].cpu(), "steps": int(state.steps)}
+
+
+def restore(ckpt: dict, flags: torch.Tensor, order: str | None = None, param: int | None = None,
+            stride: int | None = None) -> State:
+    """Rebuild the sparse representation from the flag field -- in the
+    checkpoint's ordering or another one: the paper lets the numbering be
+    chosen afresh at every restart (Sec. 8) -- and place each listed cell's
+    PDFs at its new index.  Every cell's populations are unchanged, so a run
+    continued from here is bitwise the uninterrupted one (up to the order of
+    the list)."""
+    order = ckpt["order"] if order is None else order
+    param = ckpt["param"] if param is None else param
+    nz, ny, nx = flags.shape
+    if [nx, ny, nz] != list(ckpt["dims"]):
+        raise ValueError(f"flag field {nx}x{ny}x{nz} is not the checkpoint's {ckpt['dims']}")
+    lat = build(flags, ckpt["periodic"], order, param, stride=stride)
+    dev = lat.device
+    old_cells = ckpt["cell_of"].to(dev, torch.int64)
+    if lat.n_fluid != old_cells.numel():
+        raise ValueError("the flag field does not hold the checkpoint's fluid cells")
+    new_index = lat.index_of.to(torch.int64)[old_cells]
+    if bool((new_index < 0).any()):
+        raise ValueError("a checkpointed cell is solid in this flag field")
+    params = [_params_from(d) for d in ckpt["params"]]
+    ns = None
+    if ckpt["ns"] is not None:
+        ns = torch.zeros(lat.stride, dtype=torch.float64, device=dev)
+        ns[new_index] = ckpt["ns"].to(dev)
+    st = init(lat, params if len(params) > 1 else params[0], ns=ns)
+    st.f[:, new_index] = ckpt["f"].to(dev)
+    st.steps = ckpt["steps"]
+    return st

@@ -40,7 +40,7 @@ def test_version_and_status_strings(lib):
     assert lib.lbm_version() >= 10000
     lib.lbm_status_string.restype = C.c_char_p
     lib.lbm_status_string.argtypes = [C.c_int32]
-    for s in range(0, -7, -1):
+    for s in range(0, -8, -1):
         assert lib.lbm_status_string(s) not in (None, b"unknown status")
     assert lib.lbm_status_string(-99) == b"unknown status"
 
@@ -100,7 +100,7 @@ def test_host_side_argument_errors(lib):
     assert step(N.make_params(0.8, 3 / 16, flags=3 << 8)) == N.LBM_EINVAL  # chunk not 2^k
     assert step(N.make_params(0.8, 3 / 16, flags=1 << 20)) == N.LBM_EINVAL  # unknown flag bit
     assert step(good, n=10, stride=5) == N.LBM_EINVAL                # stride < n
-    assert step(good, n_params=2) == N.LBM_EINVAL
+    assert step(good, n_params=0) == N.LBM_EINVAL
     assert step(good, a=dummy, b=dummy) == N.LBM_EINVAL              # in-place not allowed
     assert step(good, n=10, stride=(1 << 32) // 19 + 1) == N.LBM_EOVERFLOW
     # strides whose product with 19 would overflow int64 are refused, not wrapped
@@ -315,3 +315,97 @@ def test_inplace_c8_argument_errors(lib):
                {"phase": 2}, {"steps": -1}, {"stride": 9}):
         assert step(**kw) == N.LBM_EINVAL, kw
     assert step(steps=0) == N.LBM_OK  # nothing to do, no launch
+
+
+def test_parameter_set_and_batch_argument_errors(lib):
+    """Per-segment parameter sets (lbm_step, lbm_step_batch, lbm_moments,
+    lbm_objective): every rule is checked on the host before any launch."""
+    from paper_1111_1129_amd import _native as N
+    P, I32, I64, SZ = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+    lib.lbm_step.restype = I32
+    lib.lbm_step.argtypes = [C.POINTER(N.lbm_params), I32, P, I32, I64, I64, P, P, P, P, I32, I32,
+                             P, C.POINTER(SZ), P]
+    lib.lbm_step_batch.restype = I32
+    lib.lbm_step_batch.argtypes = [C.POINTER(N.lbm_params), I32, P, I32, I64, I64, P, P, P, P, P,
+                                   P, P, I32, I32, P, C.POINTER(SZ), P]
+    lib.lbm_moments.restype = I32
+    lib.lbm_moments.argtypes = [C.POINTER(N.lbm_params), I32, I64, I64, P, P, P, P, P, I32, P, P,
+                                C.POINTER(SZ), P]
+    lib.lbm_objective.restype = I32
+    lib.lbm_objective.argtypes = [C.POINTER(N.lbm_params), I32, I64, I64, P, P, P, I32, P, P,
+                                  C.POINTER(SZ), P]
+    d, e = P(4096), P(8192)
+    good = N.make_params(0.8, 3 / 16, (1e-6, 0, 0), "f32")
+
+    def params(*ps):
+        arr = (N.lbm_params * len(ps))(*ps)
+        return C.cast(arr, C.POINTER(N.lbm_params)), arr
+
+    def segs(*ts):
+        return C.cast((N.lbm_segment * len(ts))(*[N.lbm_segment(*t, 0) for t in ts]), P)
+
+    two, _keep = params(good, N.make_params(0.9, 3 / 16, (2e-6, 0, 0), "f32"))
+    ws = C.c_size_t(1 << 20)
+
+    def step(p=two, n_params=2, sg=None, n_seg=0, n=1000, stride=1024, persistent=0,
+             workspace=d, wsb=ws):
+        return lib.lbm_step(p, n_params, sg, n_seg, n, stride, d, None, d, e, 1, persistent,
+                            workspace, C.byref(wsb), None)
+
+    # size query: a segment selecting set 1 needs the table
+    q = C.c_size_t(0)
+    assert step(sg=segs((0, 300, 0), (512, 400, 1)), n_seg=2, workspace=None, wsb=q) == N.LBM_OK
+    assert q.value >= 256 + 2 * 96 + 4 * 4
+    # a set index outside [0, n_params)
+    assert step(sg=segs((0, 300, 0), (512, 400, 2)), n_seg=2) == N.LBM_EINVAL
+    assert step(sg=segs((0, 300, -1)), n_seg=1) == N.LBM_EINVAL
+    # sets differ and a segment does not start on a 256-cell tile
+    assert step(sg=segs((0, 300, 0), (300, 400, 1)), n_seg=2) == N.LBM_EINVAL
+    assert step(sg=segs((0, 300, 1), (400, 400, 0)), n_seg=2) == N.LBM_EINVAL
+    # out of order / overlapping / past n
+    assert step(sg=segs((512, 100, 1), (0, 100, 0)), n_seg=2) == N.LBM_EINVAL
+    assert step(sg=segs((0, 600, 0), (512, 100, 1)), n_seg=2) == N.LBM_EINVAL
+    assert step(sg=segs((768, 300, 1)), n_seg=1) == N.LBM_EINVAL
+    # workspace smaller than the query
+    small = C.c_size_t(q.value - 1)
+    assert step(sg=segs((0, 300, 0), (512, 400, 1)), n_seg=2, wsb=small) == N.LBM_EWORKSPACE
+    # sets that differ in storage or launch flags
+    other, _k2 = params(good, N.make_params(0.9, 3 / 16, (0, 0, 0), "f64"))
+    assert step(p=other) == N.LBM_EINVAL
+    flagged, _k3 = params(good, N.make_params(0.9, 3 / 16, (0, 0, 0), "f32", flags=1))
+    assert step(p=flagged) == N.LBM_EINVAL
+    bad, _k4 = params(good, N.make_params(0.5, 3 / 16, (0, 0, 0), "f32"))
+    assert step(p=bad) == N.LBM_EINVAL
+    # the finite check is a known flag
+    chk, _k5 = params(N.make_params(0.8, 3 / 16, (0, 0, 0), "f32", flags=N.FLAG_CHECK_FINITE))
+    assert step(p=chk, n_params=1, n=0, stride=0) == N.LBM_OK
+
+    # lbm_step_batch: codes8 needs codes, codes need tile records
+    def batch(c8=None, c16=None, recs=None):
+        return lib.lbm_step_batch(two, 2, None, 0, 1000, 1024, c8, c16, recs, d, None, d, e, 1, 0,
+                                  d, C.byref(ws), None)
+    assert batch(c8=d) == N.LBM_EINVAL
+    assert batch(c16=d) == N.LBM_EINVAL
+    assert batch(recs=d) == N.LBM_EINVAL
+    assert lib.lbm_step_batch(two, 2, None, 0, 0, 0, d, d, d, d, None, d, e, 1, 0, d,
+                              C.byref(ws), None) == N.LBM_OK  # nothing to do
+    # persistent size query through the batch entry point
+    q2 = C.c_size_t(0)
+    assert lib.lbm_step_batch(two, 2, None, 0, 1000, 1024, None, None, None, d, None, d, e, 3, 1,
+                              None, C.byref(q2), None) == N.LBM_OK and q2.value >= 256
+
+    # lbm_moments / lbm_objective take the sets too
+    tot = C.c_size_t(0)
+    assert lib.lbm_moments(two, 2, 1000, 1024, d, d, None, None, segs((0, 300, 0), (512, 400, 1)),
+                           2, d, None, C.byref(tot), None) == N.LBM_OK and tot.value > 0
+    assert lib.lbm_moments(two, 2, 1000, 1024, d, d, None, None, segs((0, 300, 3)), 1, d, None,
+                           C.byref(tot), None) == N.LBM_EINVAL
+    assert lib.lbm_moments(two, 0, 1000, 1024, d, d, None, None, None, 0, d, None, C.byref(tot),
+                           None) == N.LBM_EINVAL
+    assert lib.lbm_moments(other, 2, 1000, 1024, d, d, None, None, None, 0, d, d, C.byref(ws),
+                           None) == N.LBM_EINVAL  # storages differ
+    assert lib.lbm_objective(two, 2, 1000, 1024, d, d, None, 0, None, d, C.byref(ws),
+                             None) == N.LBM_EINVAL  # J missing
+    assert lib.lbm_objective(two, 2, 1000, 1024, d, d, None, 0, d, None, C.byref(tot),
+                             None) == N.LBM_OK and tot.value > 0  # size query
+

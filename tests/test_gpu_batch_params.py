@@ -1,0 +1,136 @@
+"""Per-geometry parameter sets in one batch (lbm_step, lbm_step_batch,
+lbm_moments, lbm_objective): every member, run with its own tau+ and force in
+one list, ends bitwise in the state a solo run of that member gives, in both
+launch forms and over the adjacency codes, and within 1e-12 of the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1111_1129_amd import _native as N
+from paper_1111_1129_amd import inputs as I
+from paper_1111_1129_amd import lattice as L
+
+from gpu_helpers import dev_flags, oracle_params, print_case, rel_err_f64
+
+pytestmark = pytest.mark.gpu
+
+# three uneven packings (edges 17, 24, 30), each with its own tau+ and force
+MEMBERS = [(17, 0.5, 0.8, (1e-5, 0.0, 0.0)), (24, 0.4, 0.65, (2e-5, 1e-6, 0.0)),
+           (30, 0.6, 1.1, (5e-6, 0.0, -3e-6))]
+STEPS = 20
+
+
+@pytest.fixture(scope="module")
+def members():
+    geoms = [I.packing_boolean(70 + k, e, e, e, 2.0, 4.0, por)
+             for k, (e, por, _, _) in enumerate(MEMBERS)]
+    batch = L.Batch([dev_flags(g) for g in geoms], [g.periodic for g in geoms], "lex",
+                    tile_align=True)
+    assert all(b % 256 == 0 for b in batch.bases) and batch.bases[1] > 0
+    return geoms, batch
+
+
+def member_params(storage, **kw):
+    return [L.params(tp, 3 / 16, force, storage, **kw) for _, _, tp, force in MEMBERS]
+
+
+def solo(geom, prm, steps):
+    lat = L.build(dev_flags(geom), geom.periodic, "lex")
+    st = L.init(lat, prm)
+    L.step(st, steps)
+    return lat, st
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32s"])
+def test_members_equal_solo_runs_both_launch_forms(members, storage):
+    geoms, batch = members
+    prms = member_params(storage, nontemporal=True, xcd_chunk=1)
+    print_case("param sets", storage, batch.total)
+    per = batch.init(prms)
+    L.step(per, STEPS)
+    pers = batch.init(prms)
+    L.step(pers, STEPS, persistent=True)
+    assert torch.equal(per.f[:, :batch.total], pers.f[:, :batch.total])
+    for k, (g, prm) in enumerate(zip(geoms, prms)):
+        lat, st = solo(g, prm, STEPS)
+        b, c = batch.bases[k], batch.counts[k]
+        assert torch.equal(per.f[:, b:b + c], st.f[:, :c]), k
+    # the sets really differ: member 0 run with member 1's set is not member 0
+    other = L.init(L.build(dev_flags(geoms[0]), geoms[0].periodic, "lex"), prms[1])
+    L.step(other, STEPS)
+    assert not torch.equal(per.f[:, :batch.counts[0]], other.f[:, :batch.counts[0]])
+
+
+def test_members_vs_oracle(members):
+    """FP64: each member of the batch within 1e-12 of the oracle run with
+    that member's parameters."""
+    geoms, batch = members
+    prms = member_params("f64")
+    st = batch.init(prms)
+    L.step(st, STEPS)
+    f = st.f.cpu().numpy()
+    for k, (g, prm) in enumerate(zip(geoms, prms)):
+        sp = O.build(g.flags, g.periodic, "lex")
+        ref = O.run(oracle_params(prm), sp.adj, O.init(sp.n_fluid), STEPS)
+        b, c = batch.bases[k], batch.counts[k]
+        assert c == sp.n_fluid
+        assert rel_err_f64(f[:, b:b + c], ref) <= 1e-12, k
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_members_over_codes(members, persistent):
+    """lbm_step_batch over 16-bit and 8-bit codes (tiles of three members,
+    padding between them) equals the full-list sweep bitwise."""
+    geoms, batch = members
+    prms = member_params("f32", nontemporal=False, xcd_chunk=4)
+    ref = batch.init(prms)
+    L.step(ref, STEPS)
+    comp = L.compress(batch.lattice, n=batch.total)
+    s16 = batch.init(prms)
+    L.step_c16(s16, comp, STEPS, persistent=persistent)
+    L.narrow(comp)
+    assert comp.n_narrow > 0
+    s8 = batch.init(prms)
+    L.step_c8(s8, comp, STEPS, persistent=persistent)
+    for st in (s16, s8):
+        for b, c in zip(batch.bases, batch.counts):
+            assert torch.equal(st.f[:, b:b + c], ref.f[:, b:b + c])
+
+
+def test_moments_and_objective_per_member(members):
+    """Totals use each member's own force (u = j + G/2); the objective of a
+    member is its x total over its cell count, bit for bit, and equals the
+    solo run's."""
+    geoms, batch = members
+    prms = member_params("f64")
+    st = batch.init(prms)
+    L.step(st, STEPS)
+    _, u, tot = L.moments(st)
+    J = L.objective(st)
+    assert tot.shape == (3, 4) and J.shape == (3,)
+    for k, (g, prm) in enumerate(zip(geoms, prms)):
+        _, sst = solo(g, prm, STEPS)
+        _, su, stot = L.moments(sst)
+        b, c = batch.bases[k], batch.counts[k]
+        assert torch.equal(u[:, b:b + c], su)
+        assert torch.equal(tot[k], stot[0])
+        assert J[k].item() == (tot[k, 1] / c).item()
+        assert torch.equal(J[k:k + 1], L.objective(sst))
+
+
+def test_nonfinite_totals_are_reported():
+    """lbm_moments with LBM_FLAG_CHECK_FINITE: a NaN population makes the call
+    return LBM_ENONFINITE (the NaN is planted from the host); a finite state
+    passes."""
+    g = I.packing_small(1)
+    lat = L.build(dev_flags(g), g.periodic, "lex")
+    st = L.init(lat, L.params(0.8, 3 / 16, (1e-6, 0, 0), "f64"))
+    L.step(st, 3)
+    L.moments(st, check_finite=True)  # finite: no error
+    st.f[4, 1000] = float("nan")
+    with pytest.raises(N.LbmError) as e:
+        L.moments(st, fields=False, check_finite=True)
+    assert e.value.status == N.LBM_ENONFINITE
+    _, _, tot = L.moments(st, fields=False)  # without the flag: no check
+    assert not torch.isfinite(tot).all()
