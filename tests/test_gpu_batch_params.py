@@ -115,7 +115,9 @@ def test_moments_and_objective_per_member(members):
         b, c = batch.bases[k], batch.counts[k]
         assert torch.equal(u[:, b:b + c], su)
         assert torch.equal(tot[k], stot[0])
-        assert J[k].item() == (tot[k, 1] / c).item()
+        # the library divides the rounded x total by the count, correctly
+        # rounded (IEEE division, as Python's float division)
+        assert J[k].item() == tot[k, 1].item() / c
         assert torch.equal(J[k:k + 1], L.objective(sst))
 
 
