@@ -359,6 +359,29 @@ lbm_status lbm_objective(const lbm_params* p, int32_t n_params, int64_t n, int64
                          void* stream);
 
 /*
+ * lbm_moments_noalloc -- lbm_moments without a workspace, for callers that
+ * cannot allocate device memory: code under stream capture, tight serving
+ * loops, harnesses that forbid allocation.  The caller still passes the
+ * state and the outputs.
+ *
+ * Same arguments as lbm_moments minus workspace / ws_bytes.  rho and u are
+ * bitwise those of lbm_moments; each total is the same double-double sum taken
+ * in another grouping (a workgroup covers several tiles), so it agrees with
+ * lbm_moments' to about 1e-30 relative before the final rounding.  The partial
+ * sums live in a fixed array of the library, 4096 partials (256 KiB) per GPU,
+ * held until the process ends; the first call on a device looks up its
+ * address (no allocation).  No input size exceeds it: the cells per workgroup
+ * grow with the segment.  Every call on one GPU shares that array, so calls
+ * that overlap on one GPU (other streams, other threads) race: order them.
+ * Errors: LBM_EINVAL, LBM_EOVERFLOW, LBM_EHIP, LBM_ENONFINITE (with
+ * LBM_FLAG_CHECK_FINITE, as lbm_moments).
+ */
+lbm_status lbm_moments_noalloc(const lbm_params* p, int32_t n_params, int64_t n, int64_t stride,
+                               const uint32_t* adj, const void* f, double* rho, double* u,
+                               const lbm_segment* seg, int32_t n_seg, double* totals,
+                               void* stream);
+
+/*
  * lbm_partition_stats -- communication metrics of cutting the list into
  * n_chunks near-equal chunks (Sec. 2: a solver on N processes cuts the 1-D
  * list into N equal chunks, some smaller by one cell; Sec. 7 and Fig. 7:

@@ -29,7 +29,8 @@ FLAG_XCD_CHUNK_SHIFT = 8
 SEGMENT_ALIGN = 256  # segments with their own parameter sets start on a sweep tile
 
 ENTRY_POINTS = ("lbm_build_adjacency", "lbm_init", "lbm_step", "lbm_step_batch",
-                "lbm_step_adjoint", "lbm_moments", "lbm_objective", "lbm_partition_stats", "lbm_compress_adjacency", "lbm_step_c16",
+                "lbm_step_adjoint", "lbm_moments", "lbm_objective", "lbm_moments_noalloc",
+                "lbm_partition_stats", "lbm_compress_adjacency", "lbm_step_c16",
                 "lbm_step_inplace", "lbm_step_adjoint_c16", "lbm_narrow_codes", "lbm_step_c8",
                 "lbm_step_inplace_c8", "lbm_version", "lbm_status_string")
 
@@ -85,6 +86,9 @@ def load(path: str = LIB_PATH):
         lib.lbm_objective.restype = I32
         lib.lbm_objective.argtypes = [C.POINTER(lbm_params), I32, I64, I64, P, P, P, I32, P, P,
                                       C.POINTER(SZ), P]
+        lib.lbm_moments_noalloc.restype = I32
+        lib.lbm_moments_noalloc.argtypes = [C.POINTER(lbm_params), I32, I64, I64, P, P, P, P, P,
+                                            I32, P, P]
         lib.lbm_step_adjoint.restype = I32
         lib.lbm_step_adjoint.argtypes = [C.POINTER(lbm_params), I64, I64, P, P, P, P, P, P, P]
         lib.lbm_moments.restype = I32
@@ -238,6 +242,15 @@ def lbm_moments(params, n, stride, adj, f, rho, u, segments, totals,
                          _ptr(adj), _ptr(f), _ptr(rho), _ptr(u), seg, n_seg, _ptr(totals),
                          None if query else _ptr(workspace), C.byref(ws), _stream(stream))
     return st, ws.value
+
+
+def lbm_moments_noalloc(params, n, stride, adj, f, rho, u, segments, totals, stream=None):
+    lib = load()
+    seg, n_seg = make_segments(segments)
+    prm, n_params = make_param_array(params)
+    return lib.lbm_moments_noalloc(C.cast(C.pointer(prm), C.POINTER(lbm_params)), n_params, n,
+                                   stride, _ptr(adj), _ptr(f), _ptr(rho), _ptr(u), seg, n_seg,
+                                   _ptr(totals), _stream(stream))
 
 
 def lbm_objective(params, n, stride, adj, f, segments, J, workspace=None, ws_bytes=0,
