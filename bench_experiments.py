@@ -332,6 +332,27 @@ def batched(a):
         t_c8, _ = timed(lambda: L.step_c8(stc, comp, steps))
         same_c8 = bool(torch.equal(stc.f[:, :tot_n], f_step))
         del stc
+        # one persistent launch over the 8-bit codes (lbm_step_batch)
+        stc = batch.init(prm)
+        L.step_c8(stc, comp, 2, persistent=True)
+        stc = batch.init(prm)
+        t_c8p, _ = timed(lambda: L.step_c8(stc, comp, steps, persistent=True))
+        same_c8p = bool(torch.equal(stc.f[:, :tot_n], f_step))
+        del stc
+        # every member with its own tau+ and force: members on 256-cell tiles,
+        # one persistent launch over the 8-bit codes
+        tb = L.Batch(flags, [g.periodic for g in geoms], "lex", stride=S, tile_align=True)
+        prms = [L.params(0.6 + 0.6 * k / max(1, count - 1), 3 / 16, (1e-6 * (1 + k % 3), 0, 0),
+                         storage, nontemporal=nt, xcd_chunk=chunk) for k in range(count)]
+        tcomp = L.narrow(L.compress(tb.lattice, n=tb.total))
+        stm = tb.init(prms)
+        L.step_c8(stm, tcomp, 2, persistent=True)
+        stm = tb.init(prms)
+        t_mp, _ = timed(lambda: L.step_c8(stm, tcomp, steps, persistent=True))
+        stm2 = tb.init(prms)
+        t_ms, _ = timed(lambda: L.step_c8(stm2, tcomp, steps))
+        same_m = bool(torch.equal(stm.f[:, :tb.total], stm2.f[:, :tb.total]))
+        del stm, stm2, tcomp, tb
         solos = []
         for fl, g in zip(flags, geoms):
             lat = L.build(fl, g.periodic, "lex")
@@ -372,6 +393,11 @@ def batched(a):
               "mflups_c8_per_step": round(tot_n * steps / t_c8 / 1e6, 1),
               "c8_narrow_tiles": comp.n_narrow, "tiles": comp.n_tiles,
               "c8_equals_per_step": same_c8,
+              "mflups_c8_persistent": round(tot_n * steps / t_c8p / 1e6, 1),
+              "c8_persistent_equals_per_step": same_c8p,
+              "mflups_c8_persistent_member_params": round(tot_n * steps / t_mp / 1e6, 1),
+              "mflups_c8_per_step_member_params": round(tot_n * steps / t_ms / 1e6, 1),
+              "member_params_persistent_equals_per_step": same_m,
               "persistent_equals_per_step": same,
               "gbs_persistent": round(BYTES[storage] * tot_n * steps / t_pers / 1e9, 1),
               "gbs_launch_per_step": round(BYTES[storage] * tot_n * steps / t_step / 1e9, 1),
