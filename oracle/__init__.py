@@ -39,10 +39,22 @@ ORDERS = {"lex": 0, "blocked": 1, "morton1": 2, "morton2": 3, "random": 4, "hilb
 OK, EINVAL, ECAPACITY, EOVERFLOW = 0, -1, -2, -3
 
 
-def compile_library(out: str = _LIB_PATH) -> str:
+# LBM_ORACLE_SANITIZE=1: build and load a copy instrumented with
+# AddressSanitizer and UndefinedBehaviorSanitizer (host code only; the process
+# must preload libasan, see tests/test_oracle_sanitized.py).
+_SANITIZE = os.environ.get("LBM_ORACLE_SANITIZE") == "1"
+_SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+              "-fno-omit-frame-pointer", "-g"]
+if _SANITIZE:
+    _LIB_PATH = os.path.join(_HERE, "_liblbm_oracle_san.so")
+
+
+def compile_library(out: str | None = None, sanitize: bool | None = None) -> str:
     """Compile the oracle's C source with gcc (always recompiles)."""
+    sanitize = _SANITIZE if sanitize is None else sanitize
+    out = out or _LIB_PATH
     cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
-           "-Wall", "-o", out + ".tmp", _SRC[0], "-lm"]
+           "-Wall", *(_SAN_FLAGS if sanitize else []), "-o", out + ".tmp", _SRC[0], "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(out + ".tmp", out)
     return out
