@@ -96,10 +96,14 @@ __global__ void k_mark_tiles(int32_t* tile_param, SegChunk chunk) {
     for (int32_t t = st.first + int32_t(threadIdx.x); t < st.last; t += blockDim.x) tile_param[t] = st.param;
 }
 
-// The TRT constants of a tile (uniform over the workgroup: scalar loads).
-__device__ __forceinline__ TrtConst tile_const(const ParamTable& tab, int64_t tile) {
-    const int32_t k = tab.tile_param ? tab.tile_param[tile] : 0;
-    const ParamEntry& e = tab.entries[k];
+// The TRT constants of a tile (uniform over the wave: scalar loads; the
+// table is read-only for the launch, which the __restrict__ kernel
+// arguments tell the compiler, so the loads stay scalar after the sweep's
+// first stores).
+__device__ __forceinline__ TrtConst tile_const(const ParamEntry* __restrict__ entries,
+                                               const int32_t* __restrict__ tile_param, int64_t tile) {
+    const int32_t k = tile_param ? tile_param[tile] : 0;
+    const ParamEntry& e = entries[k];
     TrtConst c;
     c.sp = e.sp;
     c.sm = e.sm;
@@ -145,12 +149,14 @@ __global__ __launch_bounds__(kBBlock) void k_trt_table(const typename Storage<ST
                                                        const int32_t* __restrict__ tile_rec,
                                                        const uint32_t* __restrict__ adj,
                                                        const double* __restrict__ ns, int64_t n,
-                                                       int64_t stride, ParamTable tab,
+                                                       int64_t stride,
+                                                       const ParamEntry* __restrict__ entries,
+                                                       const int32_t* __restrict__ tile_param,
                                                        int chunk_shift) {
     const int64_t tile = logical_block(chunk_shift);
     const int64_t m = tile * kBBlock + threadIdx.x;
     if (m >= n) return;
-    const TrtConst c = tile_const(tab, tile);
+    const TrtConst c = tile_const(entries, tile_param, tile);
     sweep_tile<ST, PBB, NT, SRC>(src, dst, codes8, codes, tile_rec, adj, ns, tile, m, stride, c);
 }
 
@@ -205,8 +211,10 @@ __global__ __launch_bounds__(kPThreads) void k_trt_persistent(typename Storage<S
                                                               const uint32_t* __restrict__ adj,
                                                               const double* __restrict__ ns,
                                                               int64_t n, int64_t stride,
-                                                              ParamTable tab, int n_steps,
-                                                              int chunk_shift, Barrier bar) {
+                                                              const ParamEntry* __restrict__ entries,
+                                                              const int32_t* __restrict__ tile_param,
+                                                              int n_steps, int chunk_shift,
+                                                              Barrier bar) {
     __shared__ int ok;
     __shared__ unsigned int populated;
     const int xcc = xcc_id();
@@ -226,7 +234,12 @@ __global__ __launch_bounds__(kPThreads) void k_trt_persistent(typename Storage<S
     const unsigned int mine =
         __hip_atomic_load(&bar.xcd_size[xcc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
-    const int wave = int(threadIdx.x) >> 6, lane = int(threadIdx.x) & 63;
+    // the wave index is uniform over the wave; readfirstlane lets the compiler
+    // see it, so the tile index, its record and its parameter set stay scalar
+    // (scalar loads); derived from threadIdx they were per-lane vector loads
+    // that each iteration waited for, and the walk ran ~36 % slower
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+    const int lane = int(threadIdx.x) & 63;
     const int64_t tiles = (n + kBBlock - 1) / kBBlock;
     const int64_t groups = (tiles + kGroupTiles - 1) / kGroupTiles;
     const int64_t q = int64_t(NXCD) << chunk_shift;
@@ -244,7 +257,7 @@ __global__ __launch_bounds__(kPThreads) void k_trt_persistent(typename Storage<S
             const int64_t tile = grp * kGroupTiles + my_tile_in_group;
             const int64_t m = tile * kBBlock + my_quarter;
             if (grp < groups && m < n) {
-                const TrtConst c = tile_const(tab, tile);
+                const TrtConst c = tile_const(entries, tile_param, tile);
                 sweep_tile<ST, PBB, NT, SRC>(src, dst, codes8, codes, tile_rec, adj, ns, tile, m,
                                              stride, c);
             }
@@ -303,7 +316,8 @@ lbm_status launch_table_steps(const BatchLaunch& L, hipStream_t s) {
         const T* src = (k & 1) ? b : a;
         T* dst = (k & 1) ? a : b;
         k_trt_table<ST, PBB, NT, SRC><<<g, blk, 0, s>>>(src, dst, L.codes8, L.codes, L.rec, L.adj,
-                                                        L.ns, L.n, L.stride, L.tab, L.chunk_shift);
+                                                        L.ns, L.n, L.stride, L.tab.entries,
+                                                        L.tab.tile_param, L.chunk_shift);
         if (hipGetLastError() != hipSuccess) return LBM_EHIP;
     }
     return LBM_OK;
@@ -342,9 +356,11 @@ lbm_status launch_persistent_t(const BatchLaunch& L, hipStream_t s) {
     const uint32_t* adj = L.adj;
     const double* ns = L.ns;
     int64_t n = L.n, stride = L.stride;
-    ParamTable tab = L.tab;
+    const ParamEntry* entries = L.tab.entries;
+    const int32_t* tile_param = L.tab.tile_param;
     int steps = L.n_steps, cs = L.chunk_shift_persistent;
-    void* args[] = {&a, &b, &c8, &c16, &rec, &adj, &ns, &n, &stride, &tab, &steps, &cs, &bar};
+    void* args[] = {&a, &b, &c8, &c16, &rec, &adj, &ns, &n, &stride, &entries, &tile_param, &steps,
+                    &cs, &bar};
     LBM_TRY_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(unsigned(grid)),
                                            dim3(kPThreads), args, 0, s));
     int err = 0;
