@@ -21,7 +21,7 @@ from paper_1111_1129_amd.tune import Sweeper, tune_layout, tune_ordering, candid
 
 from bench import PDF_SIZE, code_mix, sweep_bytes  # one definition of the per-update byte counts
 
-BYTES = {"f64": 376, "f64s": 376, "f32": 224, "f32s": 224, "f16s": 148}
+BYTES = {"f64": 376, "f64s": 376, "f32": 224, "f32s": 224, "f16s": 148, "f16s12": 148}
 PEAK = 8000.0
 
 
@@ -58,7 +58,7 @@ def precision(a):
     g = I.workload("large_packing", scale=a.scale)
     flags = dev_flags(g)
     sweeps = 500
-    forms = ["f64", "f64s", "f32", "f32s", "f16s"]
+    forms = ["f64", "f64s", "f32", "f32s", "f16s", "f16s12"]
     layouts = {st: tune_layout(flags, g.periodic, "lex", 0, st, sweeps=4) for st in forms}
     t_ref_codes = {}
     for gx in (1e-6, 1e-5, 1e-4):
@@ -129,7 +129,7 @@ def precision_vs_oracle(a, scale=4, sweeps=500):
     u_orc = torch.from_numpy(np.ascontiguousarray(u_orc)).cuda()
     flags = dev_flags(g)
     lat = L.build(flags, g.periodic, "lex")
-    for st in ("f64", "f64s", "f32", "f32s", "f16s"):
+    for st in ("f64", "f64s", "f32", "f32s", "f16s", "f16s12"):
         prm = L.params(0.8, 3 / 16, (1e-6, 0, 0), st)
         state = L.init(lat, prm)
         L.step(state, sweeps)

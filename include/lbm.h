@@ -78,13 +78,20 @@ typedef enum {
 
 /* PDF storage (the paper stores double precision, Sec. 7).  "Shifted" arrays
  * hold f_i - w_i.  F64 forms compute in FP64; F32/F16 forms compute in FP32.
- * Reductions (moments totals) are always accumulated in FP64. */
+ * Reductions (moments totals) are always accumulated in FP64.
+ * LBM_F16_SHIFTED_SCALED stores 2^12 (f_i - w_i) in FP16: the same bytes as
+ * LBM_F16_SHIFTED, but deviations down to 2^-26 stay in FP16's normal range
+ * (shifted FP16 turns those below 2^-14 subnormal, which is what limits its
+ * accuracy at small forcing); |f_i - w_i| must stay below 16 (a lattice
+ * Boltzmann state has 0 <= f_i <= 1).  Multiplying by 2^12 and by 2^-12 is
+ * exact, so the only rounding is the FP16 store, as in the unscaled form. */
 typedef enum {
     LBM_F64 = 0,
     LBM_F64_SHIFTED = 1,
     LBM_F32 = 2,
     LBM_F32_SHIFTED = 3,
-    LBM_F16_SHIFTED = 4
+    LBM_F16_SHIFTED = 4,
+    LBM_F16_SHIFTED_SCALED = 5
 } lbm_storage;
 
 enum {

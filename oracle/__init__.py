@@ -257,14 +257,18 @@ def run(prm: TRT, adj: np.ndarray, f: np.ndarray, n_steps: int, ns=None, n0: int
 
 def round_storage(f: np.ndarray, storage: str) -> np.ndarray:
     """Round an FP64 state to a storage type (IEEE round to nearest even) and
-    widen it back: 'f64', 'f32', 'f16' (f16 goes through f32 first, as a
-    kernel with FP32 arithmetic and FP16 storage rounds)."""
+    widen it back: 'f64', 'f32', 'f16s' (FP16 goes through FP32 first, as a
+    kernel with FP32 arithmetic and FP16 storage rounds), 'f16s12' (FP16 of
+    2^12 times the value: exact scaling, the same two roundings)."""
     if storage in ("f64", "f64s"):
         return f.copy()
     if storage in ("f32", "f32s"):
         return f.astype(np.float32).astype(np.float64)
     if storage == "f16s":
         return f.astype(np.float32).astype(np.float16).astype(np.float64)
+    if storage == "f16s12":
+        up = (f * 4096.0).astype(np.float32)
+        return up.astype(np.float16).astype(np.float64) / 4096.0
     raise KeyError(storage)
 
 

@@ -20,9 +20,10 @@ LBM_OK, LBM_EINVAL, LBM_ECAPACITY, LBM_EOVERFLOW, LBM_EWORKSPACE, LBM_EHIP, LBM_
     0, -1, -2, -3, -4, -5, -6
 LBM_ENONFINITE = -7
 ORDERS = {"lex": 0, "blocked": 1, "morton1": 2, "morton2": 3, "random": 4, "hilbert": 5}
-STORAGES = {"f64": 0, "f64s": 1, "f32": 2, "f32s": 3, "f16s": 4}
+STORAGES = {"f64": 0, "f64s": 1, "f32": 2, "f32s": 3, "f16s": 4, "f16s12": 5}
 STORAGE_DTYPE = {0: torch.float64, 1: torch.float64, 2: torch.float32, 3: torch.float32,
-                 4: torch.float16}
+                 4: torch.float16, 5: torch.float16}  # 5 holds 2^12 (f - w) as FP16
+F16_SCALE = 4096.0  # factor of the scaled shifted FP16 storage
 FLAG_NONTEMPORAL = 1
 FLAG_CHECK_FINITE = 2
 FLAG_XCD_CHUNK_SHIFT = 8

@@ -466,6 +466,7 @@ lbm_status step_batch(const lbm_params* p, int32_t n_params, const lbm_segment* 
     case LBM_F32: return launch_batch_st<LBM_F32>(L, nt, persistent, s);
     case LBM_F32_SHIFTED: return launch_batch_st<LBM_F32_SHIFTED>(L, nt, persistent, s);
     case LBM_F16_SHIFTED: return launch_batch_st<LBM_F16_SHIFTED>(L, nt, persistent, s);
+    case LBM_F16_SHIFTED_SCALED: return launch_batch_st<LBM_F16_SHIFTED_SCALED>(L, nt, persistent, s);
     default: return LBM_EINVAL;
     }
 }

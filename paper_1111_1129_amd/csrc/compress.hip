@@ -271,6 +271,7 @@ lbm_status step_coded(const lbm_params& p, int64_t n, int64_t stride, const int8
     case LBM_F32: return dispatch_coded<LBM_F32>(p, n, stride, codes8, codes, toff, adj, ns, fa, fb, n_steps, s);
     case LBM_F32_SHIFTED: return dispatch_coded<LBM_F32_SHIFTED>(p, n, stride, codes8, codes, toff, adj, ns, fa, fb, n_steps, s);
     case LBM_F16_SHIFTED: return dispatch_coded<LBM_F16_SHIFTED>(p, n, stride, codes8, codes, toff, adj, ns, fa, fb, n_steps, s);
+    case LBM_F16_SHIFTED_SCALED: return dispatch_coded<LBM_F16_SHIFTED_SCALED>(p, n, stride, codes8, codes, toff, adj, ns, fa, fb, n_steps, s);
     default: return LBM_EINVAL;
     }
 }

@@ -198,6 +198,7 @@ lbm_status step_inplace(const lbm_params& p, int64_t n, int64_t stride, const ui
     case LBM_F32: return dispatch_inplace<LBM_F32>(p, n, stride, adj, codes, codes8, rec, ns, f, phase, n_steps, s);
     case LBM_F32_SHIFTED: return dispatch_inplace<LBM_F32_SHIFTED>(p, n, stride, adj, codes, codes8, rec, ns, f, phase, n_steps, s);
     case LBM_F16_SHIFTED: return dispatch_inplace<LBM_F16_SHIFTED>(p, n, stride, adj, codes, codes8, rec, ns, f, phase, n_steps, s);
+    case LBM_F16_SHIFTED_SCALED: return dispatch_inplace<LBM_F16_SHIFTED_SCALED>(p, n, stride, adj, codes, codes8, rec, ns, f, phase, n_steps, s);
     default: return LBM_EINVAL;
     }
 }

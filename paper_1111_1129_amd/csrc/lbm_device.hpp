@@ -43,12 +43,28 @@ template <> struct Storage<LBM_F32> { using T = float; using A = float; static c
 template <> struct Storage<LBM_F32_SHIFTED> { using T = float; using A = float; static constexpr bool shifted = true; };
 template <> struct Storage<LBM_F16_SHIFTED> { using T = _Float16; using A = float; static constexpr bool shifted = true; };
 
+// FP16 holding 2^12 x the value (LBM_F16_SHIFTED_SCALED).  Scaling by a power
+// of two is exact in FP32, so loading and storing round exactly as the
+// unscaled FP16 form does, only in a range shifted down by 12 binades.
+struct Half12 {
+    _Float16 bits;
+    static constexpr float kUp = 4096.0f, kDown = 1.0f / 4096.0f;
+    __host__ __device__ explicit operator float() const { return static_cast<float>(bits) * kDown; }
+    __host__ __device__ explicit operator double() const {
+        return static_cast<double>(static_cast<float>(bits) * kDown);
+    }
+};
+template <> struct Storage<LBM_F16_SHIFTED_SCALED> { using T = Half12; using A = float; static constexpr bool shifted = true; };
+
 template <class T, class A> __device__ __forceinline__ A ld(const T* p) { return static_cast<A>(*p); }
 // Read-once streams (adjacency rows, adjacency codes): nontemporal loads keep
 // them from displacing the PDF lines whose partial reuse by neighbouring
 // cells the caches serve (measured: 2 % faster sweep over codes in FP64).
 template <class T> __device__ __forceinline__ T ld_stream(const T* p) {
     return __builtin_nontemporal_load(p);
+}
+__device__ __forceinline__ Half12 ld_stream(const Half12* p) {
+    return Half12{__builtin_nontemporal_load(&p->bits)};
 }
 // FP32 -> FP16 conversion rounds to nearest even (IEEE default mode).  The
 // value is first rounded to A: the empty asm hides how it was computed, so the
@@ -57,17 +73,24 @@ template <class T> __device__ __forceinline__ T ld_stream(const T* p) {
 // not in others, which would make their results differ in the last bit).
 template <class T, class A, bool NT> __device__ __forceinline__ void st(T* p, A v) {
     if constexpr (!std::is_same_v<T, A>) asm("" : "+v"(v));
-    if constexpr (NT)
+    if constexpr (std::is_same_v<T, Half12>) {
+        const _Float16 b = static_cast<_Float16>(v * Half12::kUp);  // exact scaling, one rounding
+        if constexpr (NT)
+            __builtin_nontemporal_store(b, &p->bits);
+        else
+            p->bits = b;
+    } else if constexpr (NT) {
         __builtin_nontemporal_store(static_cast<T>(v), p);
-    else
+    } else {
         *p = static_cast<T>(v);
+    }
 }
 
 inline size_t storage_bytes(int st) {
     switch (st) {
     case LBM_F64: case LBM_F64_SHIFTED: return 8;
     case LBM_F32: case LBM_F32_SHIFTED: return 4;
-    case LBM_F16_SHIFTED: return 2;
+    case LBM_F16_SHIFTED: case LBM_F16_SHIFTED_SCALED: return 2;
     default: return 0;
     }
 }

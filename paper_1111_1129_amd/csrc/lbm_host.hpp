@@ -25,7 +25,7 @@ inline lbm_status after_launch() {
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
-inline bool valid_storage(int st) { return st >= LBM_F64 && st <= LBM_F16_SHIFTED; }
+inline bool valid_storage(int st) { return st >= LBM_F64 && st <= LBM_F16_SHIFTED_SCALED; }
 
 // TRT parameters usable for a sweep: tau+ > 1/2 and tau- > 1/2 (magic > 0),
 // everything finite.

@@ -238,6 +238,7 @@ lbm_status moments_call(const lbm_params* p, int32_t n_params, int64_t n, int64_
     case LBM_F32: st = launch_moments<LBM_F32>(p, n, stride, adj, f, rho, u, seg, n_seg, totals, objective, partial, s); break;
     case LBM_F32_SHIFTED: st = launch_moments<LBM_F32_SHIFTED>(p, n, stride, adj, f, rho, u, seg, n_seg, totals, objective, partial, s); break;
     case LBM_F16_SHIFTED: st = launch_moments<LBM_F16_SHIFTED>(p, n, stride, adj, f, rho, u, seg, n_seg, totals, objective, partial, s); break;
+    case LBM_F16_SHIFTED_SCALED: st = launch_moments<LBM_F16_SHIFTED_SCALED>(p, n, stride, adj, f, rho, u, seg, n_seg, totals, objective, partial, s); break;
     default: return LBM_EINVAL;
     }
     if (st != LBM_OK || !totals || !(p[0].flags & LBM_FLAG_CHECK_FINITE)) return st;
@@ -350,6 +351,7 @@ extern "C" lbm_status lbm_moments_noalloc(const lbm_params* p, int32_t n_params,
     case LBM_F32: st = launch_moments_noalloc<LBM_F32>(p, n, stride, adj, f, rho, u, seg, n_seg, totals, partial, s); break;
     case LBM_F32_SHIFTED: st = launch_moments_noalloc<LBM_F32_SHIFTED>(p, n, stride, adj, f, rho, u, seg, n_seg, totals, partial, s); break;
     case LBM_F16_SHIFTED: st = launch_moments_noalloc<LBM_F16_SHIFTED>(p, n, stride, adj, f, rho, u, seg, n_seg, totals, partial, s); break;
+    case LBM_F16_SHIFTED_SCALED: st = launch_moments_noalloc<LBM_F16_SHIFTED_SCALED>(p, n, stride, adj, f, rho, u, seg, n_seg, totals, partial, s); break;
     default: return LBM_EINVAL;
     }
     if (st != LBM_OK || !totals || !(p[0].flags & LBM_FLAG_CHECK_FINITE)) return st;

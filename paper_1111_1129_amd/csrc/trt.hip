@@ -51,7 +51,8 @@ __global__ __launch_bounds__(kBlock) void k_init(typename Storage<ST>::T* __rest
     const int64_t m = int64_t(blockIdx.x) * kBlock + threadIdx.x;
     if (m >= n) return;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) f[i * stride + m] = static_cast<T>(static_cast<typename Storage<ST>::A>(e.v[i]));
+    for (int i = 0; i < Q; ++i)
+        st<T, typename Storage<ST>::A, false>(f + i * stride + m, static_cast<typename Storage<ST>::A>(e.v[i]));
 }
 
 template <int ST, bool PBB, bool NT>
@@ -131,6 +132,7 @@ extern "C" lbm_status lbm_init(const lbm_params* p, int64_t n, int64_t stride, v
     case LBM_F32: return launch_init<LBM_F32>(*p, n, stride, f, rho0, u0, s);
     case LBM_F32_SHIFTED: return launch_init<LBM_F32_SHIFTED>(*p, n, stride, f, rho0, u0, s);
     case LBM_F16_SHIFTED: return launch_init<LBM_F16_SHIFTED>(*p, n, stride, f, rho0, u0, s);
+    case LBM_F16_SHIFTED_SCALED: return launch_init<LBM_F16_SHIFTED_SCALED>(*p, n, stride, f, rho0, u0, s);
     default: return LBM_EINVAL;
     }
 }
@@ -173,6 +175,7 @@ extern "C" lbm_status lbm_step_batch(const lbm_params* p, int32_t n_params,
     case LBM_F32: return dispatch_step<LBM_F32>(*p, n, stride, adj, ns, f_a, f_b, n_steps, s);
     case LBM_F32_SHIFTED: return dispatch_step<LBM_F32_SHIFTED>(*p, n, stride, adj, ns, f_a, f_b, n_steps, s);
     case LBM_F16_SHIFTED: return dispatch_step<LBM_F16_SHIFTED>(*p, n, stride, adj, ns, f_a, f_b, n_steps, s);
+    case LBM_F16_SHIFTED_SCALED: return dispatch_step<LBM_F16_SHIFTED_SCALED>(*p, n, stride, adj, ns, f_a, f_b, n_steps, s);
     default: return LBM_EINVAL;
     }
 }

@@ -90,23 +90,25 @@ def _time_sweeps(lat, prm, sweeps, stream, sweeper=None):
 def tune_layout(flags: torch.Tensor, periodic: int, order: str = "lex", param: int = 0,
                 storage: str = "f64", force=(1e-6, 0.0, 0.0), sweeps: int = 6,
                 candidates: list[int] | None = None,
-                chunks: tuple = (1, 4, 16, 64, 0), finalists: int = 4,
-                sweep: str = "full") -> Layout:
+                chunks: tuple = (1, 4, 16, 64, 0), finalists: int = 5,
+                sweep: str = "full", final_seconds: float = 0.25,
+                final_max_sweeps: int = 2000) -> Layout:
     """Time the candidate layouts on this geometry and return the fastest.
 
     `sweep` names the sweep being tuned (see Sweeper); timed runs use an even
     number of sweeps.
 
     Two stages: every candidate is timed over `sweeps` sweeps; the best
-    `finalists` are timed again, twice each and interleaved, over 3 x
-    `sweeps` sweeps, and the best mean wins (short timings alone are noisy
-    enough to mis-rank layouts a few percent apart)."""
+    `finalists` are timed again, twice each and interleaved, each time for
+    about `final_seconds` (at least 3 x `sweeps`, at most
+    `final_max_sweeps` sweeps), and the best mean wins.  Short bursts alone
+    mis-rank layouts a few percent apart, and a layout's rate over a burst of
+    a few milliseconds is not its sustained rate over seconds of streaming."""
     n = L.count_fluid(flags, periodic, order, param)
     cands = candidates or candidate_strides(n)
     sweeps += sweeps % 2
     table = []
     stream = torch.cuda.current_stream()
-    lats = {}
     for S in cands:
         sw = Sweeper(L.build(flags, periodic, order, param, stride=S), sweep)
         for nt in (False, True):
@@ -116,15 +118,20 @@ def tune_layout(flags: torch.Tensor, periodic: int, order: str = "lex", param: i
                 table.append((S, nt, chunk, round(n / t / 1e6, 1)))
         del sw
     top = sorted(table, key=lambda r: -r[3])[:max(1, finalists)]
+    by_stride = {}
+    for S, nt, chunk, rate in top:
+        k = int(final_seconds * rate * 1e6 / max(n, 1))  # sweeps in final_seconds at the burst rate
+        k = max(3 * sweeps, min(final_max_sweeps, k))
+        by_stride.setdefault(S, []).append((nt, chunk, k + k % 2))
     totals = {}
     for _ in range(2):
-        for S, nt, chunk, _r in top:
-            if S not in lats:
-                lats.clear()
-                lats[S] = Sweeper(L.build(flags, periodic, order, param, stride=S), sweep)
-            prm = L.params(0.8, 3.0 / 16.0, force, storage, nontemporal=nt, xcd_chunk=chunk)
-            t = _time_sweeps(lats[S].lat, prm, 3 * sweeps, stream, lats[S])
-            totals[(S, nt, chunk)] = totals.get((S, nt, chunk), 0.0) + t
+        for S, cfgs in by_stride.items():
+            sw = Sweeper(L.build(flags, periodic, order, param, stride=S), sweep)
+            for nt, chunk, k in cfgs:
+                prm = L.params(0.8, 3.0 / 16.0, force, storage, nontemporal=nt, xcd_chunk=chunk)
+                t = _time_sweeps(sw.lat, prm, k, stream, sw)
+                totals[(S, nt, chunk)] = totals.get((S, nt, chunk), 0.0) + t
+            del sw
     (S, nt, chunk), tsum = min(totals.items(), key=lambda kv: kv[1])
     best = Layout(S, nt, chunk, n / (tsum / 2) / 1e6)
     best.table = table

@@ -63,14 +63,15 @@ def test_bench_precision_and_crop_baseline():
     d = json.loads(res.stdout.strip().splitlines()[-1])
     assert d["dtype"] == "f64" and d["config"]["workload"].startswith("large_packing")
     p = d["precision"]
-    for st in ("f64s", "f32", "f32s", "f16s"):
+    for st in ("f64s", "f32", "f32s", "f16s", "f16s12"):
         for key in ("mflups", "speedup_vs_f64", "u_rel_l2", "u_rel_max", "sweep"):
             assert key in p[st], (st, key)
         assert p[st]["mflups"] > 0 and 0 <= p[st]["u_rel_l2"] < 1
     assert p["f64s"]["u_rel_l2"] < 1e-9          # same arithmetic type, other rounding
     assert p["f32s"]["u_rel_l2"] < p["f32"]["u_rel_l2"]  # the shift keeps FP32 accurate
     crop = p["vs_oracle_on_crop"]
-    assert set(crop) == {"f64", "f64s", "f32", "f32s", "f16s"}
+    assert set(crop) == {"f64", "f64s", "f32", "f32s", "f16s", "f16s12"}
+    assert crop["f16s12"]["u_rel_l2"] < crop["f16s"]["u_rel_l2"]  # no subnormal deviations
     assert crop["f64"]["u_rel_l2"] < 1e-10 and crop["f64s"]["u_rel_l2"] < 1e-10
     c = d["cpu_baseline"]
     assert c["kind"] == "oracle" and "crop" in c["sample"] and c["value"] > 0

@@ -136,7 +136,7 @@ def test_small_packing_vs_oracle_with_pbb():
     assert rel_err_f64(st.f.cpu().numpy()[:, :n], orc[:, :n], shifted=True) <= 1e-12
 
 
-@pytest.mark.parametrize("storage", ["f64", "f64s", "f32", "f32s", "f16s"])
+@pytest.mark.parametrize("storage", ["f64", "f64s", "f32", "f32s", "f16s", "f16s12"])
 def test_bitwise_equal_to_full_list_sweep(storage):
     g = I.packing_small(1)
     print_case("compress", "bitwise", storage)
@@ -219,7 +219,7 @@ def test_narrow_codes_are_exact(order, param):
         assert not ok.any()
 
 
-@pytest.mark.parametrize("storage", ["f64", "f64s", "f32", "f32s", "f16s"])
+@pytest.mark.parametrize("storage", ["f64", "f64s", "f32", "f32s", "f16s", "f16s12"])
 def test_c8_bitwise_equal_to_full_list_sweep(storage):
     g = I.random_flags(11, 64, 64, 48, 0.7)
     print_case("narrow", "bitwise", storage, "random_flags 64x64x48 periodic xyz")

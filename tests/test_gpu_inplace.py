@@ -32,7 +32,7 @@ def one_array(lat, prm, f0, steps, ns=None, comp=None, split=None, c8=False):
     return st
 
 
-@pytest.mark.parametrize("storage", ["f64", "f64s", "f32", "f32s", "f16s"])
+@pytest.mark.parametrize("storage", ["f64", "f64s", "f32", "f32s", "f16s", "f16s12"])
 @pytest.mark.parametrize("codes", ["adj", "c16", "c8"])
 def test_even_steps_bitwise_equal_two_array(storage, codes):
     """Lexicographic order of a fully periodic box: narrow, 16-bit and escape

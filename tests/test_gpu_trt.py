@@ -161,19 +161,36 @@ def test_poiseuille_on_gpu():
     np.testing.assert_allclose(u[0].cpu().numpy(), exact, rtol=1e-9)
 
 
-@pytest.mark.parametrize("storage", ["f64", "f64s", "f32", "f16s"])
+def encode(f64: np.ndarray, storage: str) -> np.ndarray:
+    """Host values -> the array a storage form keeps (exactly representable
+    inputs: round_storage first)."""
+    if storage == "f16s12":
+        return (f64 * 4096.0).astype(np.float16)
+    dt = {"f64": np.float64, "f64s": np.float64, "f32": np.float32, "f32s": np.float32,
+          "f16s": np.float16}[storage]
+    return f64.astype(dt)
+
+
+def decode(stored: np.ndarray, storage: str) -> np.ndarray:
+    out = stored.astype(np.float64)
+    return out / 4096.0 if storage == "f16s12" else out
+
+
+def storage_shifted(storage: str) -> bool:
+    return storage in ("f64s", "f32s", "f16s", "f16s12")
+
+
+@pytest.mark.parametrize("storage", ["f64", "f64s", "f32", "f16s", "f16s12"])
 def test_moments_vs_oracle(small, storage):
     g, sp, lat = small
-    shifted = storage.endswith("s")
+    shifted = storage_shifted(storage)
     prm = L.params(0.8, 3 / 16, (1e-5, 2e-6, 0), storage)
     n = sp.n_fluid
-    f0 = random_state(n, 7, amp=1e-2, shifted=shifted, stride=lat.stride)
-    dt = {"f64": np.float64, "f64s": np.float64, "f32": np.float32, "f16s": np.float16}[storage]
-    f0 = f0.astype(dt)
+    f0 = O.round_storage(random_state(n, 7, amp=1e-2, shifted=shifted, stride=lat.stride), storage)
     st = L.init(lat, prm)
-    st.f.copy_(torch.from_numpy(f0))
+    st.f.copy_(torch.from_numpy(encode(f0, storage)))
     rho, u, tot = L.moments(st)
-    orho, ou, otot = O.moments(oracle_params(prm), sp.adj, f0.astype(np.float64), shifted, 0, n)
+    orho, ou, otot = O.moments(oracle_params(prm), sp.adj, f0, shifted, 0, n)
     np.testing.assert_allclose(rho.cpu().numpy(), orho, rtol=1e-14, atol=0)
     np.testing.assert_allclose(u.cpu().numpy(), ou, rtol=0, atol=1e-16)
     t = tot.cpu().numpy()[0]
@@ -197,32 +214,54 @@ def test_moments_segments_and_determinism(small):
         np.testing.assert_allclose(t1[k].cpu().numpy(), ot, rtol=1e-13, atol=1e-18)
 
 
-@pytest.mark.parametrize("storage", ["f32", "f32s", "f16s"])
+def storage_ulp(x: np.ndarray, storage: str) -> np.ndarray:
+    """Spacing of the storage grid at |x| (FP64 values)."""
+    if storage == "f16s12":
+        return np.spacing(np.abs(x * 4096.0).astype(np.float16)).astype(np.float64) / 4096.0
+    dt = np.float16 if storage == "f16s" else np.float32
+    return np.spacing(np.abs(x).astype(dt)).astype(np.float64)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f32s", "f16s", "f16s12"])
 def test_reduced_precision_one_step(small, storage):
     """One step from a stored FP32/FP16 state: the GPU computes in FP32, the
     oracle in FP64 on the same widened inputs and rounds to the storage type.
     Bound: one storage ulp of the result (the rounding decision may differ)
     plus the FP32 evaluation error, 64 eps32 of the largest value involved."""
     g, sp, lat = small
-    shifted = storage.endswith("s")
+    shifted = storage_shifted(storage)
     prm = L.params(0.8, 3 / 16, (1e-5, 0, 0), storage)
     n = sp.n_fluid
-    f0 = random_state(n, 9, amp=2e-2, shifted=shifted, stride=lat.stride)
-    dt = np.float16 if storage == "f16s" else np.float32
-    f0 = f0.astype(dt)
+    f0 = O.round_storage(random_state(n, 9, amp=2e-2, shifted=shifted, stride=lat.stride), storage)
     st = L.init(lat, prm)
-    st.f.copy_(torch.from_numpy(f0))
+    st.f.copy_(torch.from_numpy(encode(f0, storage)))
     L.step(st, 1)
-    gpu = cells(st.f.cpu().numpy().astype(np.float64), n)
-    exact = cells(orun(prm, sp, f0.astype(np.float64), 1), n)
+    gpu = cells(decode(st.f.cpu().numpy(), storage), n)
+    exact = cells(orun(prm, sp, f0, 1), n)
     f0 = cells(f0, n)
     orc = O.round_storage(exact, storage)
-    scale = np.abs(f0.astype(np.float64)).max() if shifted else 1.0
-    ulp = np.spacing(np.abs(exact).astype(dt)).astype(np.float64)
-    tol = ulp + 64 * np.finfo(np.float32).eps * scale
+    scale = np.abs(f0).max() if shifted else 1.0
+    tol = storage_ulp(exact, storage) + 64 * np.finfo(np.float32).eps * scale
     assert (np.abs(gpu - orc) <= tol).all()
     # and the result is not trivially the input
-    assert np.abs(gpu - f0.astype(np.float64)).max() > 10 * tol.max()
+    assert np.abs(gpu - f0).max() > 10 * tol.max()
+
+
+def test_scaled_fp16_keeps_small_deviations():
+    """At body force 1e-6 the deviations f - w fall below FP16's normal range;
+    the scaled form keeps them, the plain shifted form rounds them to a
+    subnormal grid: after 200 sweeps its velocity is far closer to FP64's."""
+    g = I.packing_small(1)
+    lat = L.build(dev_flags(g), g.periodic, "lex")
+    u = {}
+    for storage in ("f64s", "f16s", "f16s12"):
+        st = L.init(lat, L.params(0.8, 3 / 16, (1e-6, 0, 0), storage))
+        L.step(st, 200)
+        u[storage] = L.moments(st)[1]
+    err = {k: float(torch.linalg.vector_norm(u[k] - u["f64s"]) / torch.linalg.vector_norm(u["f64s"]))
+           for k in ("f16s", "f16s12")}
+    print_case("scaled fp16 error", err)
+    assert err["f16s12"] < 0.2 * err["f16s"]
 
 
 def sampled_step_vs_oracle(lat, sp, prm, st, advance, ranges, seed):

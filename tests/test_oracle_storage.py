@@ -75,3 +75,32 @@ def test_round_storage_keeps_shape():
     x = np.linspace(-1, 1, 19 * 7).reshape(19, 7)
     for st in ("f64", "f32", "f32s", "f16s"):
         assert O.round_storage(x, st).shape == (19, 7)
+
+
+# FP16 holding 2^12 x the value: the same IEEE roundings on a grid 12 binades lower
+S12_CASES = [
+    (2.0 ** -12 * (1 + 2.0 ** -11), 2.0 ** -12),               # tie -> even
+    (2.0 ** -12 * (1 + 3 * 2.0 ** -11), 2.0 ** -12 * (1 + 2.0 ** -9)),
+    (1e-6, 1074 * 2.0 ** -30),                                 # normal in the scaled form: 1073.74 -> 1074
+    (2.0 ** -26, 2.0 ** -26),                                  # smallest normal of the scaled form
+    (2.0 ** -36, 2.0 ** -36),                                  # smallest subnormal of the scaled form
+    (0.75 * 2.0 ** -36, 2.0 ** -36),
+    (-(1e-6), -(1074 * 2.0 ** -30)),
+    (65504.0 / 4096, 65504.0 / 4096),                          # largest finite value: 15.99...
+    (16.0, np.inf),                                            # 65536 overflows
+]
+
+
+@pytest.mark.filterwarnings("ignore:overflow encountered in cast")
+@pytest.mark.parametrize("x,want", S12_CASES)
+def test_round_storage_f16_scaled(x, want):
+    got = O.round_storage(np.array([[x]]), "f16s12")
+    assert got.dtype == np.float64 and got[0, 0] == want
+
+
+def test_scaled_f16_is_f16_of_the_scaled_value():
+    """On values whose scaled FP32 rounding is exact, the scaled form is the
+    unscaled form of 4096 x the value, divided back."""
+    x = np.array([[3.0e-5, -7.5e-7, 1.2e-3, 0.25]])
+    assert np.array_equal(O.round_storage(x, "f16s12") * 4096.0,
+                          O.round_storage(x * 4096.0, "f16s"))
