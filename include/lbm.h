@@ -209,8 +209,8 @@ lbm_status lbm_init(const lbm_params* p, int64_t n, int64_t stride, void* f, dou
  * store out_i at element i*stride + m of the destination array.  In shifted
  * storage the same map acts on f - w with rho read as the density deviation.
  *
- *  p, n_params  (host) n_params >= 1 parameter sets.  All sets share one
- *               storage type and one set of launch flags (those of p[0]).
+ *  p, n_params  (host) 1 <= n_params <= 65536 parameter sets.  All sets share
+ *               one storage type and one set of launch flags (those of p[0]).
  *  seg, n_seg   (host) batch layout, or NULL/0 for one geometry [0, n).  Segments
  *               lie inside [0, n), in increasing order, without overlap
  *               (adjacency entries already carry each member's base).  Segment k
@@ -234,7 +234,7 @@ lbm_status lbm_init(const lbm_params* p, int64_t n, int64_t stride, void* f, dou
  * Every member's state is bitwise what a run of that member alone (same
  * parameters) gives, in either launch form.
  * Errors: LBM_EINVAL (NULL p/adj/f_a/f_b, f_a == f_b, n < 0, stride < n,
- * n_params < 1, sets differing in storage or flags, bad storage, tau_plus <= 1/2,
+ * n_params outside [1, 65536], sets differing in storage or flags, bad storage, tau_plus <= 1/2,
  * non-finite parameters, bad segments: out of order, overlapping, outside
  * [0, n), param_index outside [0, n_params), a segment not starting on a tile
  * while sets differ), LBM_EOVERFLOW (19*stride >= 2^32), LBM_EWORKSPACE,

@@ -58,6 +58,7 @@ inline lbm_status check_layout(int64_t n, int64_t stride) {
 // names a set other than 0, every non-empty segment starts on a tile of
 // kSegmentAlign cells, so no tile holds cells of two segments.
 constexpr int64_t kSegmentAlign = 256;
+constexpr int32_t kMaxParamSets = 65536;  // parameter sets of one call
 
 inline bool uses_param_sets(const lbm_segment* seg, int32_t n_seg) {
     for (int32_t k = 0; k < n_seg; ++k)

@@ -210,7 +210,7 @@ lbm_status moments_call(const lbm_params* p, int32_t n_params, int64_t n, int64_
                         const uint32_t* adj, const void* f, double* rho, double* u,
                         const lbm_segment* seg, int32_t n_seg, double* totals, double* objective,
                         void* workspace, size_t* ws_bytes, void* stream) {
-    if (!p || n_params < 1) return LBM_EINVAL;
+    if (!p || n_params < 1 || n_params > kMaxParamSets) return LBM_EINVAL;
     if (lbm_status st = check_layout(n, stride); st != LBM_OK) return st;
     if (!valid_segments(seg, n_seg, n, n_params)) return LBM_EINVAL;
     int64_t largest = (seg && n_seg > 0) ? 0 : n;
@@ -331,7 +331,7 @@ extern "C" lbm_status lbm_moments_noalloc(const lbm_params* p, int32_t n_params,
                                           int64_t stride, const uint32_t* adj, const void* f,
                                           double* rho, double* u, const lbm_segment* seg,
                                           int32_t n_seg, double* totals, void* stream) {
-    if (!p || n_params < 1 || !adj || !f) return LBM_EINVAL;
+    if (!p || n_params < 1 || n_params > kMaxParamSets || !adj || !f) return LBM_EINVAL;
     if (lbm_status st = check_layout(n, stride); st != LBM_OK) return st;
     if (!valid_segments(seg, n_seg, n, n_params)) return LBM_EINVAL;
     for (int32_t k = 0; k < n_params; ++k) {

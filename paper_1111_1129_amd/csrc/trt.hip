@@ -144,7 +144,8 @@ extern "C" lbm_status lbm_step_batch(const lbm_params* p, int32_t n_params,
                                      const double* ns, void* f_a, void* f_b, int32_t n_steps,
                                      int32_t persistent, void* workspace, size_t* ws_bytes,
                                      void* stream) {
-    if (!p || n_params < 1 || n_seg < 0 || (n_seg > 0 && !seg)) return LBM_EINVAL;
+    if (!p || n_params < 1 || n_params > kMaxParamSets || n_seg < 0 || (n_seg > 0 && !seg))
+        return LBM_EINVAL;
     const bool table = persistent || uses_param_sets(seg, n_seg);
     if (table && !workspace) {  // size query
         if (!ws_bytes) return LBM_EINVAL;

@@ -376,6 +376,7 @@ def test_parameter_set_and_batch_argument_errors(lib):
     assert step(p=flagged) == N.LBM_EINVAL
     bad, _k4 = params(good, N.make_params(0.5, 3 / 16, (0, 0, 0), "f32"))
     assert step(p=bad) == N.LBM_EINVAL
+    assert step(n_params=65537) == N.LBM_EINVAL  # beyond the documented limit (host check only)
     # the finite check is a known flag
     chk, _k5 = params(N.make_params(0.8, 3 / 16, (0, 0, 0), "f32", flags=N.FLAG_CHECK_FINITE))
     assert step(p=chk, n_params=1, n=0, stride=0) == N.LBM_OK
