@@ -352,7 +352,15 @@ def batched(a):
         stm2 = tb.init(prms)
         t_ms, _ = timed(lambda: L.step_c8(stm2, tcomp, steps))
         same_m = bool(torch.equal(stm.f[:, :tb.total], stm2.f[:, :tb.total]))
-        del stm, stm2, tcomp, tb
+        # all steps in one graph launch (the per-step launches captured once)
+        stg = tb.init(prms)
+        graph = L.StepGraph(stg, steps, tcomp)
+        graph.replay()
+        stg2 = tb.init(prms)
+        stg.f.copy_(stg2.f)
+        t_mg, _ = timed(graph.replay)
+        same_g = bool(torch.equal(stg.f[:, :tb.total], stm2.f[:, :tb.total]))
+        del stm, stm2, stg, stg2, graph, tcomp, tb
         solos = []
         for fl, g in zip(flags, geoms):
             lat = L.build(fl, g.periodic, "lex")
@@ -398,6 +406,8 @@ def batched(a):
               "mflups_c8_persistent_member_params": round(tot_n * steps / t_mp / 1e6, 1),
               "mflups_c8_per_step_member_params": round(tot_n * steps / t_ms / 1e6, 1),
               "member_params_persistent_equals_per_step": same_m,
+              "mflups_c8_graph_member_params": round(tot_n * steps / t_mg / 1e6, 1),
+              "member_params_graph_equals_per_step": same_g,
               "persistent_equals_per_step": same,
               "gbs_persistent": round(BYTES[storage] * tot_n * steps / t_pers / 1e9, 1),
               "gbs_launch_per_step": round(BYTES[storage] * tot_n * steps / t_step / 1e9, 1),

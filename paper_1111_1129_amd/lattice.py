@@ -346,10 +346,14 @@ def step_c16(state: State, comp: Compressed, n_steps: int = 1, stream=None,
 
 class StepGraph:
     """n_steps sweeps of a State captured once in a HIP graph and replayed as
-    one graph launch, for geometries so small that launching a sweep costs
-    about as much as the sweep.  n_steps is even, so each replay leaves the
-    result in state.f.  The sweeps read the full list (comp None), the
-    16-bit codes, or the 8-bit codes where comp has been narrowed; results
+    one graph launch: for geometries so small that launching a sweep costs
+    about as much as the sweep, and for a batch that has to advance many
+    steps in one launch (every step keeps the hardware's dynamic workgroup
+    dispatch, which the persistent launch gives up).  n_steps is even, so
+    each replay leaves the result in state.f.  The sweeps read the full list
+    (comp None), the 16-bit codes, or the 8-bit codes where comp has been
+    narrowed; a batch whose segments select parameter sets goes through
+    lbm_step_batch with a workspace allocated before the capture.  Results
     are bitwise those of the same eager calls.  The captured work is kernel
     launches only (no allocation, no memset); the buffers and parameters are
     fixed at capture."""
@@ -360,13 +364,33 @@ class StepGraph:
         if comp is not None:
             assert comp.n == state.n and comp.codes.shape[1] == lat.stride
         self.state, self.n_steps, self.comp = state, n_steps, comp
+        self.ws, self.wsn = None, 0
+        if _needs_workspace(False, state.segments):
+            codes8, codes, recs = self._codes()
+            rc, self.wsn = N.lbm_step_batch(state.params, state.n, lat.stride, codes8, codes, recs,
+                                            lat.adj, state.ns, state.f, state.g, n_steps, 0,
+                                            state.segments, query=True)
+            N._check("lbm_step_batch", rc)
+            self.ws = torch.empty(max(self.wsn, 1), dtype=torch.uint8, device=lat.device)
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):  # launches go to the capturing stream
             self._launch()
 
+    def _codes(self):
+        comp = self.comp
+        if comp is None:
+            return None, None, None
+        return comp.codes8, comp.codes, comp.tile_records
+
     def _launch(self):
         st, lat, comp = self.state, self.state.lattice, self.comp
-        if comp is None:
+        if self.ws is not None:
+            codes8, codes, recs = self._codes()
+            rc, _ = N.lbm_step_batch(st.params, st.n, lat.stride, codes8, codes, recs, lat.adj,
+                                     st.ns, st.f, st.g, self.n_steps, 0, st.segments, self.ws,
+                                     self.wsn)
+            N._check("lbm_step_batch", rc)
+        elif comp is None:
             rc, _ = N.lbm_step(st.params, st.n, lat.stride, lat.adj, st.ns, st.f, st.g,
                                self.n_steps)
             N._check("lbm_step", rc)

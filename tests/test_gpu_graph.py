@@ -39,6 +39,31 @@ def test_graph_replays_match_eager_steps(codes, storage):
     assert st.steps == 40
 
 
+@pytest.mark.parametrize("codes", ["full", "c8"])
+def test_graph_of_a_batch_with_parameter_sets(codes):
+    """A batch whose members keep their own tau+ and force, captured once:
+    every replay equals the same eager steps, bitwise."""
+    geoms = [I.packing_boolean(40 + k, e, e, e, 2.0, 4.0, 0.5) for k, e in enumerate((19, 26, 13))]
+    batch = L.Batch([dev_flags(g) for g in geoms], [g.periodic for g in geoms], "lex",
+                    tile_align=True)
+    prms = [L.params(0.7 + 0.15 * k, 3 / 16, (1e-5 * (k + 1), 0, 0), "f32s") for k in range(3)]
+    comp = None
+    if codes == "c8":
+        comp = L.narrow(L.compress(batch.lattice, n=batch.total))
+    print_case("graph batch", codes, batch.total)
+    ref = batch.init(prms)
+    st = batch.init(prms)
+    graph = L.StepGraph(st, 8, comp)
+    for r in range(3):
+        graph.replay()
+        if comp is None:
+            L.step(ref, 8)
+        else:
+            L.step_c8(ref, comp, 8)
+        torch.cuda.synchronize()
+        assert torch.equal(st.f[:, :batch.total], ref.f[:, :batch.total]), r
+
+
 def test_graph_with_partial_bounce_back():
     g = I.pbb_box(4, n=24)
     lat = L.build(dev_flags(g), g.periodic, "lex", 0)
