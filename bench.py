@@ -249,6 +249,13 @@ def rel_errors(u, ref):
             float(d.abs().max() / ref.abs().max()))
 
 
+def print_finals(what: str, layout) -> None:
+    """The tuner's finalists and their sustained rates (stderr)."""
+    for (S, nt, chunk), rate in sorted(layout.finals.items(), key=lambda kv: -kv[1]):
+        print(f"tune final {what}: stride={S} nt={int(nt)} chunk={chunk}: {rate:.0f} MFLUPS",
+              file=sys.stderr)
+
+
 def run_form(flags, geom, a, storage, kind, sweeps, layout=None):
     """One storage form: tune its layout (unless given), sweep `sweeps` times
     from rest, return (seconds per sweep, u [3][n] FP64, Layout)."""
@@ -258,6 +265,7 @@ def run_form(flags, geom, a, storage, kind, sweeps, layout=None):
     if layout is None:
         layout = (tune_layout(flags, geom.periodic, a.order, a.param, storage, sweep=kind)
                   if a.layout == "tuned" else Layout(None, False, 0))
+        print_finals(f"{storage} {kind}", layout)
     lat = L.build(flags, geom.periodic, a.order, a.param, stride=layout.stride)
     sw = Sweeper(lat, kind)
     prm = L.params(0.8, 3.0 / 16.0, (1e-6, 0.0, 0.0), storage, nontemporal=layout.nontemporal,
@@ -364,6 +372,7 @@ def main():
         stride, nt, chunk = lay.stride, lay.nontemporal, lay.xcd_chunk
         for row in lay.table:
             print("tune stride=%d nt=%d chunk=%d: %.0f MFLUPS" % row, file=sys.stderr)
+        print_finals(f"{a.storage} {a.sweep}", lay)
     elif a.layout == "given":
         stride, nt, chunk = (a.stride or None), bool(a.nt), a.chunk
     else:

@@ -26,6 +26,7 @@ class Layout:
     xcd_chunk: int
     mflups: float = 0.0
     table: list = dataclasses.field(default_factory=list)
+    finals: dict = dataclasses.field(default_factory=dict)
 
 
 def _next_pow2(n: int) -> int:
@@ -99,11 +100,14 @@ def tune_layout(flags: torch.Tensor, periodic: int, order: str = "lex", param: i
     number of sweeps.
 
     Two stages: every candidate is timed over `sweeps` sweeps; the best
-    `finalists` are timed again, twice each and interleaved, each time for
-    about `final_seconds` (at least 3 x `sweeps`, at most
-    `final_max_sweeps` sweeps), and the best mean wins.  Short bursts alone
-    mis-rank layouts a few percent apart, and a layout's rate over a burst of
-    a few milliseconds is not its sustained rate over seconds of streaming."""
+    configuration of every stride and the best `finalists` overall are timed
+    again, twice each and interleaved, each time for about `final_seconds`
+    (at least 3 x `sweeps`, at most `final_max_sweeps` sweeps), and the best
+    mean wins.  Short bursts alone mis-rank layouts a few percent apart, and
+    a layout's rate over a burst of a few milliseconds is not its sustained
+    rate over seconds of streaming, so no stride is dropped on its burst
+    rate alone.  The returned Layout carries the burst table (`table`) and
+    the finalists' sustained rates (`finals`, MFLUPS)."""
     n = L.count_fluid(flags, periodic, order, param)
     cands = candidates or candidate_strides(n)
     sweeps += sweeps % 2
@@ -117,7 +121,12 @@ def tune_layout(flags: torch.Tensor, periodic: int, order: str = "lex", param: i
                 t = _time_sweeps(sw.lat, prm, sweeps, stream, sw)
                 table.append((S, nt, chunk, round(n / t / 1e6, 1)))
         del sw
-    top = sorted(table, key=lambda r: -r[3])[:max(1, finalists)]
+    ranked = sorted(table, key=lambda r: -r[3])
+    top = ranked[:max(1, finalists)]
+    for S in cands:  # the best configuration of every stride
+        row = next(r for r in ranked if r[0] == S)
+        if row not in top:
+            top.append(row)
     by_stride = {}
     for S, nt, chunk, rate in top:
         k = int(final_seconds * rate * 1e6 / max(n, 1))  # sweeps in final_seconds at the burst rate
@@ -135,6 +144,7 @@ def tune_layout(flags: torch.Tensor, periodic: int, order: str = "lex", param: i
     (S, nt, chunk), tsum = min(totals.items(), key=lambda kv: kv[1])
     best = Layout(S, nt, chunk, n / (tsum / 2) / 1e6)
     best.table = table
+    best.finals = {key: round(n / (t / 2) / 1e6, 1) for key, t in totals.items()}
     return best
 
 

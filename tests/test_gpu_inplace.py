@@ -176,3 +176,7 @@ def test_sweeper_kinds_and_tuner():
                       sweep="c16")
     assert lay.stride >= lat.n_fluid and lay.stride % 64 == 0
     assert lay.xcd_chunk in (1, 0) and lay.mflups > 0
+    # every candidate stride reaches the sustained finals
+    from paper_1111_1129_amd.tune import candidate_strides
+    assert {key[0] for key in lay.finals} == set(candidate_strides(lat.n_fluid))
+    assert (lay.stride, lay.nontemporal, lay.xcd_chunk) in lay.finals
