@@ -148,8 +148,12 @@ def code_only(text: str) -> str:
 
 def kernel_source_hash(kind: str) -> str:
     """Hash of the sweep's code (kernel file + device header, comments
-    ignored): a profile summary is trusted only while it matches."""
+    ignored) and of the device compile flags (include paths left out): a
+    profile summary is trusted only while it matches."""
+    import importlib
+    build = importlib.import_module("paper_1111_1129_amd.build")
     h = hashlib.sha256()
+    h.update(" ".join(f for f in build.compile_flags() if not f.startswith("-I")).encode())
     for rel in kernel_sources(kind):
         with open(os.path.join(ROOT, rel)) as fh:
             h.update(code_only(fh.read()).encode())

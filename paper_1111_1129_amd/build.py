@@ -34,11 +34,11 @@ def compile_flags() -> list[str]:
     return [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
             # packed FP32 instructions are kept out of every kernel
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            # a*b+c is fused only inside one source expression: which products
-            # the compiler fuses then does not depend on the code around the
-            # collision, so every kernel that inlines it (one launch per step,
-            # persistent, over adjacency codes, in place) rounds identically
-            "-ffp-contract=on",
+            # no fused a*b+c: every product and sum is rounded on its own
+            # (IEEE), so every kernel that inlines the collision (one launch
+            # per step, persistent, over adjacency codes, in place) rounds
+            # identically whatever code surrounds it
+            "-ffp-contract=off",
             f"-I{INCLUDE}", f"-I{CSRC}"]
 
 

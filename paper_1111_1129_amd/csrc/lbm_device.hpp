@@ -67,10 +67,12 @@ __device__ __forceinline__ Half12 ld_stream(const Half12* p) {
     return Half12{__builtin_nontemporal_load(&p->bits)};
 }
 // FP32 -> FP16 conversion rounds to nearest even (IEEE default mode).  The
-// value is first rounded to A: the empty asm hides how it was computed, so the
-// compiler cannot fold the conversion into a mixed-precision FMA that rounds
-// an unrounded product-sum straight to FP16 (it does so in some kernels and
-// not in others, which would make their results differ in the last bit).
+// value is first rounded to A: device code is built without contraction, so
+// no fused product-sum exists that the conversion could absorb, and the empty
+// asm hides how the value was computed, so no mixed-precision instruction can
+// round an unrounded result straight to FP16 (with contraction on, the
+// compiler once did so in one kernel and not in another, and their results
+// differed in the last bit).
 template <class T, class A, bool NT> __device__ __forceinline__ void st(T* p, A v) {
     if constexpr (!std::is_same_v<T, A>) asm("" : "+v"(v));
     if constexpr (std::is_same_v<T, Half12>) {
