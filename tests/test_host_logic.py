@@ -81,3 +81,28 @@ def test_crop_sample_keeps_aspect_and_fraction():
     c = crop_sample(f, 0.125)
     assert tuple(c.shape) == (32, 16, 64)
     assert c.is_contiguous()
+
+
+def test_device_build_flags_fix_the_rounding():
+    """Device code is built without floating-point contraction (every sweep
+    variant then rounds each product and sum on its own, the basis of their
+    bitwise equality) and without packed FP32 instructions; the profile hash
+    covers these flags."""
+    import importlib
+    build = importlib.import_module("paper_1111_1129_amd.build")
+    flags = build.compile_flags()
+    assert "-ffp-contract=off" in flags
+    assert not any(f.startswith("-ffp-contract=") and f != "-ffp-contract=off" for f in flags)
+    i = flags.index("-packed-fp32-ops")
+    assert flags[i - 3:i] == ["-Xclang", "-target-feature", "-Xclang"]
+    assert not any("fast-math" in f or f.startswith("-Ofast") for f in flags)
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    h = bench.kernel_source_hash("c8")
+    orig = build.compile_flags
+    try:
+        build.compile_flags = lambda: [f.replace("=off", "=on") for f in orig()]
+        assert bench.kernel_source_hash("c8") != h
+    finally:
+        build.compile_flags = orig
+    assert bench.kernel_source_hash("c8") == h
