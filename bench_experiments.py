@@ -152,6 +152,13 @@ ADJ_BYTES_FULL = 3 * 152 + 8 + 16 + 72
 ADJ_BYTES_C16 = 3 * 152 + 8 + 16 + 36 + 80 / 256
 
 
+def adj_bytes_c8(narrow: float, escape: float) -> float:
+    """Bytes per cell-step of the adjoint over 8-bit codes: 18 int8 codes in
+    narrow tiles, 18 int16 elsewhere, the uint32 list in escape tiles."""
+    return (3 * 152 + 8 + 16 + 18 * narrow + 36 * (1 - narrow - escape) + 72 * escape
+            + 80 / 256)
+
+
 # ---------------------------------------------------------------------------
 def adjoint(a):
     """Gradient of the mean flux w.r.t. the PBB solid fraction: adjoint with
@@ -159,14 +166,14 @@ def adjoint(a):
     n_edge = 128 // a.scale
     g = I.pbb_box(4, n=n_edge)
     flags = dev_flags(g)
-    # layout of the adjoint kernel (over the 16-bit codes, as the gradient
+    # layout of the adjoint kernel (over the 8-/16-bit codes, as the gradient
     # uses it): row stride x store policy x XCD mapping, each timed over 20
     # adjoint steps; the fastest is used for the run
     n = L.count_fluid(flags, g.periodic, "lex")
     table = []
     for S in sorted({L.aligned_stride(n), candidate_strides(n)[-2]}):
         lat = L.build(flags, g.periodic, "lex", stride=S)
-        comp = L.compress(lat)
+        comp = L.narrow(L.compress(lat))
         nsl = torch.zeros(S, dtype=torch.float64, device="cuda")
         nsl[:n] = 0.5
         for nt in (False, True):
@@ -179,8 +186,9 @@ def adjoint(a):
 
                 def adj_steps(reps):
                     for _ in range(reps):
-                        N.lbm_step_adjoint_c16(prm, n, S, comp.codes, comp.tile_records, lat.adj,
-                                               st.f, nsl, lam, lam2, gr)
+                        N.lbm_step_adjoint_c8(prm, n, S, comp.codes8, comp.codes,
+                                              comp.tile_records, lat.adj, st.f, nsl, lam, lam2,
+                                              gr)
                 adj_steps(1)
                 t, _ = timed(lambda: adj_steps(20))
                 table.append((S, nt, chunk, round(t / 20 * 1e6, 1)))
@@ -199,7 +207,9 @@ def adjoint(a):
     t_fwd, (J, ckpts, _) = timed(lambda: AD.forward_states(lat, prm, ns, T, k, comp))
     t_bwd, grad = timed(lambda: AD.adjoint_gradient(lat, prm, ns, T, k, ckpts, comp))
     grad = grad.cpu().numpy()[:n]
-    # adjoint kernel alone, over the codes and over the full list
+    # adjoint kernel alone, over the 8-bit codes, the 16-bit codes and the full list
+    narrow, escape = code_mix(comp)
+    bytes_c8 = adj_bytes_c8(narrow, escape)
     lam = torch.zeros((19, S), dtype=torch.float64, device="cuda")
     lam2 = torch.empty_like(lam)
     gr = torch.zeros(S, dtype=torch.float64, device="cuda")
@@ -209,12 +219,20 @@ def adjoint(a):
             N.lbm_step_adjoint_c16(prm, n, S, comp.codes, comp.tile_records, lat.adj, ckpts[0],
                                    ns, lam, lam2, gr)
 
+    def c8_steps(reps):
+        for _ in range(reps):
+            N.lbm_step_adjoint_c8(prm, n, S, comp.codes8, comp.codes, comp.tile_records, lat.adj,
+                                  ckpts[0], ns, lam, lam2, gr)
+
     def full_steps(reps):
         for _ in range(reps):
             N.lbm_step_adjoint(prm, n, S, lat.adj, ckpts[0], ns, lam, lam2, gr)
-    c16_steps(1)
-    t_adj, _ = timed(lambda: c16_steps(20))
+    c8_steps(1)
+    t_adj, _ = timed(lambda: c8_steps(20))
     t_adj /= 20
+    c16_steps(1)
+    t_adj_c16, _ = timed(lambda: c16_steps(20))
+    t_adj_c16 /= 20
     full_steps(1)
     t_adj_full, _ = timed(lambda: full_steps(20))
     t_adj_full /= 20
@@ -277,10 +295,13 @@ def adjoint(a):
           "checkpoint_every": k, "J_mean_ux": float(J), "forward_s": round(t_fwd, 4),
           "backward_s": round(t_bwd, 4), "backward_over_forward": round(t_bwd / t_fwd, 2),
           "layout": [S, nt_best, chunk_best], "layout_table_us": table,
-          "adjoint_step_us": round(t_adj * 1e6, 1),
-          "adjoint_bytes_per_cell": ADJ_BYTES_C16,
-          "adjoint_gbs": round(ADJ_BYTES_C16 * n / t_adj / 1e9, 1),
-          "adjoint_hbm_frac": round(ADJ_BYTES_C16 * n / t_adj / 1e9 / PEAK, 4),
+          "adjoint_step_us": round(t_adj * 1e6, 1), "adjoint_codes": "8-bit",
+          "narrow_cells": round(narrow, 4), "escape_cells": round(escape, 4),
+          "adjoint_bytes_per_cell": round(bytes_c8, 2),
+          "adjoint_gbs": round(bytes_c8 * n / t_adj / 1e9, 1),
+          "adjoint_hbm_frac": round(bytes_c8 * n / t_adj / 1e9 / PEAK, 4),
+          "adjoint_c16_step_us": round(t_adj_c16 * 1e6, 1),
+          "adjoint_c16_gbs": round(ADJ_BYTES_C16 * n / t_adj_c16 / 1e9, 1),
           "adjoint_full_list_step_us": round(t_adj_full * 1e6, 1),
           "adjoint_full_list_gbs": round(ADJ_BYTES_FULL * n / t_adj_full / 1e9, 1),
           "fd_cells": 32, "fd_h": 1e-4, "fd_rel_err_max": float(errs.max()),

@@ -318,6 +318,24 @@ lbm_status lbm_step_adjoint_c16(const lbm_params* p, int64_t n, int64_t stride,
                                 void* stream);
 
 /*
+ * lbm_step_adjoint_c8 -- lbm_step_adjoint_c16 reading the 8-bit codes of
+ * lbm_narrow_codes in narrow tiles (552 - 54 bytes per cell-step there), the
+ * 16-bit codes in the other escape-free tiles and adj in tiles with escapes.
+ * Results are bitwise those of lbm_step_adjoint (every form rebuilds the same
+ * slots).
+ *
+ *  codes8  int8 [18][stride] from lbm_narrow_codes for the same codes and
+ *        tile_records (which carry the narrow flags).  The other arguments as
+ *        lbm_step_adjoint_c16.
+ * Errors: as lbm_step_adjoint_c16, and LBM_EINVAL for NULL codes8.
+ */
+lbm_status lbm_step_adjoint_c8(const lbm_params* p, int64_t n, int64_t stride,
+                               const int8_t* codes8, const int16_t* codes,
+                               const int32_t* tile_records, const uint32_t* adj,
+                               const void* f_t, const double* ns, const double* lam_next,
+                               double* lam_t, double* grad_ns, void* stream);
+
+/*
  * lbm_moments -- macroscopic fields and FP64 totals of a stored state (the
  * density and velocity of each fluid cell, from the populations the next pull
  * sweep of Sec. 7 gathers; the totals are what the mass-conservation and

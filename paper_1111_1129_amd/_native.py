@@ -32,8 +32,9 @@ SEGMENT_ALIGN = 256  # segments with their own parameter sets start on a sweep t
 ENTRY_POINTS = ("lbm_build_adjacency", "lbm_init", "lbm_step", "lbm_step_batch",
                 "lbm_step_adjoint", "lbm_moments", "lbm_objective", "lbm_moments_noalloc",
                 "lbm_partition_stats", "lbm_compress_adjacency", "lbm_step_c16",
-                "lbm_step_inplace", "lbm_step_adjoint_c16", "lbm_narrow_codes", "lbm_step_c8",
-                "lbm_step_inplace_c8", "lbm_version", "lbm_status_string")
+                "lbm_step_inplace", "lbm_step_adjoint_c16", "lbm_step_adjoint_c8",
+                "lbm_narrow_codes", "lbm_step_c8", "lbm_step_inplace_c8", "lbm_version",
+                "lbm_status_string")
 
 
 class lbm_geom(C.Structure):
@@ -108,6 +109,9 @@ def load(path: str = LIB_PATH):
         lib.lbm_step_adjoint_c16.restype = I32
         lib.lbm_step_adjoint_c16.argtypes = [C.POINTER(lbm_params), I64, I64, P, P, P, P, P, P,
                                              P, P, P]
+        lib.lbm_step_adjoint_c8.restype = I32
+        lib.lbm_step_adjoint_c8.argtypes = [C.POINTER(lbm_params), I64, I64, P, P, P, P, P, P,
+                                            P, P, P, P]
         lib.lbm_narrow_codes.restype = I32
         lib.lbm_narrow_codes.argtypes = [I64, I64, P, P, P, C.POINTER(C.c_int64), P,
                                          C.POINTER(SZ), P]
@@ -328,6 +332,14 @@ def lbm_step_adjoint_c16(params: lbm_params, n, stride, codes, tile_records, adj
                                        _ptr(tile_records), _ptr(adj), _ptr(f_t), _ptr(ns),
                                        _ptr(lam_next), _ptr(lam_t), _ptr(grad_ns),
                                        _stream(stream))
+
+
+def lbm_step_adjoint_c8(params: lbm_params, n, stride, codes8, codes, tile_records, adj, f_t,
+                        ns, lam_next, lam_t, grad_ns, stream=None):
+    return load().lbm_step_adjoint_c8(C.byref(params), n, stride, _ptr(codes8), _ptr(codes),
+                                      _ptr(tile_records), _ptr(adj), _ptr(f_t), _ptr(ns),
+                                      _ptr(lam_next), _ptr(lam_t), _ptr(grad_ns),
+                                      _stream(stream))
 
 
 def lbm_step_inplace_c8(params: lbm_params, n, stride, adj, codes8, codes, tile_records, ns, f,

@@ -46,8 +46,8 @@ def forward_states(lat: Lattice, prm, ns: torch.Tensor, T: int, k: int,
 def adjoint_gradient(lat: Lattice, prm, ns: torch.Tensor, T: int, k: int, ckpts=None,
                      comp: Compressed | None = None):
     """dJ/dns [stride] (float64) by checkpointed reverse sweeps (the segment
-    recomputation reads the 8-/16-bit codes as the forward does, the adjoint
-    steps the 16-bit codes)."""
+    recomputation and the adjoint steps read the 8-bit codes in narrow tiles
+    and the 16-bit codes elsewhere, as the forward does)."""
     comp = codes_of(lat, comp)
     if ckpts is None:
         _, ckpts, _ = forward_states(lat, prm, ns, T, k, comp)
@@ -68,9 +68,9 @@ def adjoint_gradient(lat: Lattice, prm, ns: torch.Tensor, T: int, k: int, ckpts=
                                ns, buf[j - 1], buf[j], 1)
             N._check("lbm_step_c8", st)
         for t in range(t1 - 1, t0 - 1, -1):
-            rc = N.lbm_step_adjoint_c16(prm, n, S, comp.codes, comp.tile_records, lat.adj,
-                                        buf[t - t0], ns, lam, lam_prev, grad)
-            N._check("lbm_step_adjoint_c16", rc)
+            rc = N.lbm_step_adjoint_c8(prm, n, S, comp.codes8, comp.codes, comp.tile_records,
+                                       lat.adj, buf[t - t0], ns, lam, lam_prev, grad)
+            N._check("lbm_step_adjoint_c8", rc)
             lam, lam_prev = lam_prev, lam
     return grad
 

@@ -22,7 +22,7 @@
 namespace lbm {
 
 constexpr int kAdjBlock = 256;
-static_assert(kAdjBlock == kCodeTile, "a workgroup of k_adjoint_c16 is one code tile");
+static_assert(kAdjBlock == kCodeTile, "a workgroup of k_adjoint_coded is one code tile");
 
 // The adjoint of one cell m whose 19 slots A (A[0] = m, A[k+1] = the slot it
 // pulls direction k + 1 from) are known.
@@ -108,33 +108,47 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(const double* __restrict_
     adjoint_cell<PBB, NT>(f_t, A, ns, lam_next, lam_t, grad, m, stride, c);
 }
 
-// Same, with the slots rebuilt from the 16-bit codes of lbm_compress_adjacency
-// (a workgroup is one 256-cell code tile; a tile with escapes reads adj).
-template <bool PBB, bool NT>
-__global__ __launch_bounds__(kAdjBlock) void k_adjoint_c16(const double* __restrict__ f_t,
-                                                           const int16_t* __restrict__ codes,
-                                                           const int32_t* __restrict__ tile_rec,
-                                                           const uint32_t* __restrict__ adj,
-                                                           const double* __restrict__ ns,
-                                                           const double* __restrict__ lam_next,
-                                                           double* __restrict__ lam_t,
-                                                           double* __restrict__ grad, int64_t n,
-                                                           int64_t stride, TrtConst c,
-                                                           int chunk_shift) {
+// Same, with the slots rebuilt from the adjacency codes of
+// lbm_compress_adjacency (a workgroup is one 256-cell code tile): with C8 the
+// 8-bit codes of a narrow tile (lbm_narrow_codes), otherwise the 16-bit codes;
+// a tile with escapes reads adj.  The branch is uniform over the workgroup and
+// every form rebuilds the same slots, so the result does not depend on it.
+template <bool PBB, bool NT, bool C8>
+__global__ __launch_bounds__(kAdjBlock) void k_adjoint_coded(const double* __restrict__ f_t,
+                                                             const int8_t* __restrict__ codes8,
+                                                             const int16_t* __restrict__ codes,
+                                                             const int32_t* __restrict__ tile_rec,
+                                                             const uint32_t* __restrict__ adj,
+                                                             const double* __restrict__ ns,
+                                                             const double* __restrict__ lam_next,
+                                                             double* __restrict__ lam_t,
+                                                             double* __restrict__ grad, int64_t n,
+                                                             int64_t stride, TrtConst c,
+                                                             int chunk_shift) {
     const int64_t tile = logical_block(chunk_shift);
     const int64_t m = tile * kAdjBlock + threadIdx.x;
     if (m >= n) return;
     const int32_t* rec = tile_rec + tile * kCodeRec;  // uniform over the workgroup
     uint32_t A[Q];
     A[0] = uint32_t(m);
-    if (rec[Q - 1] != 0) {
+    const uint32_t S = uint32_t(stride), mm = uint32_t(m);
+    if (C8 && rec[Q] != 0) {
+        int32_t cd[Q - 1];
+#pragma unroll
+        for (int k = 0; k < Q - 1; ++k) cd[k] = ld_stream(codes8 + k * stride + m);
+#pragma unroll
+        for (int k = 0; k < Q - 1; ++k) {
+            const uint32_t i = k + 1;
+            A[i] = cd[k] == int32_t(kCode8Bounce) ? uint32_t(opp(int(i))) * S + mm
+                                                  : i * S + uint32_t(rec[k]) + mm + uint32_t(cd[k]);
+        }
+    } else if (rec[Q - 1] != 0) {
 #pragma unroll
         for (int k = 0; k < Q - 1; ++k) A[k + 1] = ld_stream(adj + k * stride + m);
     } else {
         int32_t cd[Q - 1];
 #pragma unroll
         for (int k = 0; k < Q - 1; ++k) cd[k] = ld_stream(codes + k * stride + m);
-        const uint32_t S = uint32_t(stride), mm = uint32_t(m);
 #pragma unroll
         for (int k = 0; k < Q - 1; ++k) {
             const uint32_t i = k + 1;
@@ -191,13 +205,16 @@ extern "C" lbm_status lbm_step_adjoint(const lbm_params* p, int64_t n, int64_t s
     return after_launch();
 }
 
-extern "C" lbm_status lbm_step_adjoint_c16(const lbm_params* p, int64_t n, int64_t stride,
-                                           const int16_t* codes, const int32_t* tile_records,
-                                           const uint32_t* adj, const void* f_t,
-                                           const double* ns, const double* lam_next,
-                                           double* lam_t, double* grad_ns, void* stream) {
-    if (!valid_params(p) || !codes || !tile_records || !adj || !f_t || !lam_next || !lam_t ||
-        n <= 0)
+namespace lbm {
+
+template <bool C8>
+lbm_status step_adjoint_coded(const lbm_params* p, int64_t n, int64_t stride,
+                              const int8_t* codes8, const int16_t* codes,
+                              const int32_t* tile_records, const uint32_t* adj, const void* f_t,
+                              const double* ns, const double* lam_next, double* lam_t,
+                              double* grad_ns, void* stream) {
+    if (!valid_params(p) || (C8 && !codes8) || !codes || !tile_records || !adj || !f_t ||
+        !lam_next || !lam_t || n <= 0)
         return LBM_EINVAL;
     if (p->storage != LBM_F64 && p->storage != LBM_F64_SHIFTED) return LBM_EINVAL;
     if (lbm_status st = check_layout(n, stride); st != LBM_OK) return st;
@@ -208,11 +225,32 @@ extern "C" lbm_status lbm_step_adjoint_c16(const lbm_params* p, int64_t n, int64
     const dim3 g{unsigned(grid_blocks(n, kAdjBlock, cs))}, b{unsigned(kAdjBlock)};
     const bool nt = p->flags & LBM_FLAG_NONTEMPORAL;
     if (ns) {
-        if (nt) k_adjoint_c16<true, true><<<g, b, 0, s>>>(f, codes, tile_records, adj, ns, lam_next, lam_t, grad_ns, n, stride, c, cs);
-        else k_adjoint_c16<true, false><<<g, b, 0, s>>>(f, codes, tile_records, adj, ns, lam_next, lam_t, grad_ns, n, stride, c, cs);
+        if (nt) k_adjoint_coded<true, true, C8><<<g, b, 0, s>>>(f, codes8, codes, tile_records, adj, ns, lam_next, lam_t, grad_ns, n, stride, c, cs);
+        else k_adjoint_coded<true, false, C8><<<g, b, 0, s>>>(f, codes8, codes, tile_records, adj, ns, lam_next, lam_t, grad_ns, n, stride, c, cs);
     } else {
-        if (nt) k_adjoint_c16<false, true><<<g, b, 0, s>>>(f, codes, tile_records, adj, ns, lam_next, lam_t, nullptr, n, stride, c, cs);
-        else k_adjoint_c16<false, false><<<g, b, 0, s>>>(f, codes, tile_records, adj, ns, lam_next, lam_t, nullptr, n, stride, c, cs);
+        if (nt) k_adjoint_coded<false, true, C8><<<g, b, 0, s>>>(f, codes8, codes, tile_records, adj, ns, lam_next, lam_t, nullptr, n, stride, c, cs);
+        else k_adjoint_coded<false, false, C8><<<g, b, 0, s>>>(f, codes8, codes, tile_records, adj, ns, lam_next, lam_t, nullptr, n, stride, c, cs);
     }
     return after_launch();
+}
+
+}  // namespace lbm
+
+extern "C" lbm_status lbm_step_adjoint_c16(const lbm_params* p, int64_t n, int64_t stride,
+                                           const int16_t* codes, const int32_t* tile_records,
+                                           const uint32_t* adj, const void* f_t,
+                                           const double* ns, const double* lam_next,
+                                           double* lam_t, double* grad_ns, void* stream) {
+    return step_adjoint_coded<false>(p, n, stride, nullptr, codes, tile_records, adj, f_t, ns,
+                                     lam_next, lam_t, grad_ns, stream);
+}
+
+extern "C" lbm_status lbm_step_adjoint_c8(const lbm_params* p, int64_t n, int64_t stride,
+                                          const int8_t* codes8, const int16_t* codes,
+                                          const int32_t* tile_records, const uint32_t* adj,
+                                          const void* f_t, const double* ns,
+                                          const double* lam_next, double* lam_t,
+                                          double* grad_ns, void* stream) {
+    return step_adjoint_coded<true>(p, n, stride, codes8, codes, tile_records, adj, f_t, ns,
+                                    lam_next, lam_t, grad_ns, stream);
 }

@@ -263,6 +263,29 @@ def test_adjoint_c16_argument_errors(lib):
     assert call(stride=(1 << 32) // 19 + 1) == N.LBM_EOVERFLOW
 
 
+def test_adjoint_c8_argument_errors(lib):
+    from paper_1111_1129_amd import _native as N
+    P = C.c_void_p
+    lib.lbm_step_adjoint_c8.restype = C.c_int32
+    lib.lbm_step_adjoint_c8.argtypes = [C.POINTER(N.lbm_params), C.c_int64, C.c_int64, P, P, P,
+                                        P, P, P, P, P, P, P]
+    f64 = N.make_params(0.8, 3 / 16, storage="f64s")
+    d = P(4096)
+
+    def call(p=f64, n=10, stride=10, codes8=d, codes=d, recs=d, lam_next=d):
+        return lib.lbm_step_adjoint_c8(C.byref(p), n, stride, codes8, codes, recs, d, d, None,
+                                       lam_next, d, None, None)
+
+    assert call(p=N.make_params(0.8, 3 / 16, storage="f16s")) == N.LBM_EINVAL  # FP64 only
+    assert call(codes8=None) == N.LBM_EINVAL
+    assert call(codes=None) == N.LBM_EINVAL
+    assert call(recs=None) == N.LBM_EINVAL
+    assert call(lam_next=None) == N.LBM_EINVAL          # no seed through this entry
+    assert call(n=0) == N.LBM_EINVAL
+    assert call(stride=9) == N.LBM_EINVAL
+    assert call(stride=(1 << 32) // 19 + 1) == N.LBM_EOVERFLOW
+
+
 def test_c8_argument_errors(lib):
     from paper_1111_1129_amd import _native as N
     P = C.c_void_p

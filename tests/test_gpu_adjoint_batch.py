@@ -83,16 +83,23 @@ def test_adjoint_launch_options_are_bitwise_identical():
         assert torch.equal(lt, outs[0][0]) and torch.equal(gr, outs[0][1])
 
 
-@pytest.mark.parametrize("order", ["lex", "random"])
+@pytest.mark.parametrize("order", ["lex", "morton2", "random"])
 def test_adjoint_over_codes_is_bitwise_the_adjoint(order):
-    """The adjoint step reading 16-bit codes (escape tiles fall back to the
-    full list; the random order escapes almost everywhere) equals the plain
-    adjoint step bit for bit."""
+    """The adjoint step reading 16-bit codes, and reading 8-bit codes in
+    narrow tiles, equals the plain adjoint step bit for bit.  On this box the
+    lexicographic order has only narrow tiles, the 2-bit Z curve a mix of
+    16-bit and escape tiles, the random order escapes almost everywhere, so
+    every branch of both coded kernels runs."""
     g = I.pbb_box(4, n=64)
-    print_case("adjoint c16", order, "pbb_box 64^3")
+    print_case("adjoint c16 / c8", order, "pbb_box 64^3")
     lat = L.build(dev_flags(g), g.periodic, order, 5 if order == "random" else 0)
     n, S = lat.n_fluid, lat.stride
-    comp = L.compress(lat)
+    comp = L.narrow(L.compress(lat))
+    rec = comp.tile_records.cpu().numpy()
+    if order == "lex":
+        assert rec[:, 19].all()
+    if order == "morton2":
+        assert (rec[:, 18] > 0).any() and (rec[:, 18] == 0).any() and not rec[:, 19].any()
     if order == "random":
         assert comp.n_escapes > 0
     ns = torch.zeros(S, dtype=torch.float64, device="cuda")
@@ -104,18 +111,22 @@ def test_adjoint_over_codes_is_bitwise_the_adjoint(order):
     prm = L.params(0.8, 3 / 16, (1e-5, 0, 0), "f64s")
     for sf in (ns, None):  # with and without partial bounce-back
         outs = []
-        for c16 in (False, True):
+        for form in ("full", "c16", "c8"):
             lt = torch.zeros((19, S), dtype=torch.float64, device="cuda")
             gr = torch.zeros(S, dtype=torch.float64, device="cuda")
-            if c16:
+            gr_arg = gr if sf is not None else None
+            if form == "c16":
                 rc = N.lbm_step_adjoint_c16(prm, n, S, comp.codes, comp.tile_records, lat.adj, f,
-                                            sf, lam, lt, gr if sf is not None else None)
+                                            sf, lam, lt, gr_arg)
+            elif form == "c8":
+                rc = N.lbm_step_adjoint_c8(prm, n, S, comp.codes8, comp.codes, comp.tile_records,
+                                           lat.adj, f, sf, lam, lt, gr_arg)
             else:
-                rc = N.lbm_step_adjoint(prm, n, S, lat.adj, f, sf, lam, lt,
-                                        gr if sf is not None else None)
+                rc = N.lbm_step_adjoint(prm, n, S, lat.adj, f, sf, lam, lt, gr_arg)
             assert rc == 0
             outs.append((lt[:, :n].clone(), gr[:n].clone()))
-        assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+        for lt, gr in outs[1:]:
+            assert torch.equal(outs[0][0], lt) and torch.equal(outs[0][1], gr)
 
 
 def test_gradient_vs_oracle_with_checkpoints(pbb):
