@@ -152,12 +152,23 @@ def _needs_workspace(persistent: bool, segments) -> bool:
     return bool(persistent) or any(len(t) > 2 and t[2] != 0 for t in (segments or ()))
 
 
-def _step_workspace(state: State, persistent: bool, segments, query):
+def _hold(t: torch.Tensor | None, stream) -> torch.Tensor | None:
+    """A scratch tensor allocated on torch's current stream but used by work
+    queued on `stream`: keep its memory from being handed out again until
+    that work is done (it is freed when the caller returns, before the
+    asynchronous kernels have run)."""
+    if t is not None and stream is not None:
+        t.record_stream(stream)
+    return t
+
+
+def _step_workspace(state: State, persistent: bool, segments, query, stream=None):
     if not _needs_workspace(persistent, segments):
         return None, 0
     st, wsn = query()
     N._check("lbm_step", st)
-    return torch.empty(max(wsn, 1), dtype=torch.uint8, device=state.lattice.device), wsn
+    ws = torch.empty(max(wsn, 1), dtype=torch.uint8, device=state.lattice.device)
+    return _hold(ws, stream), wsn
 
 
 def set_state(state: State, f: torch.Tensor):
@@ -172,7 +183,7 @@ def step(state: State, n_steps: int = 1, persistent: bool = False, segments=None
     segments = state.segments if segments is None else segments
     ws, wsn = _step_workspace(state, persistent, segments, lambda: N.lbm_step(
         state.params, state.n, lat.stride, lat.adj, state.ns, state.f, state.g, n_steps, 1,
-        segments, query=True))
+        segments, query=True), stream)
     st, _ = N.lbm_step(state.params, state.n, lat.stride, lat.adj, state.ns, state.f, state.g,
                        n_steps, int(persistent), segments, ws, wsn, stream)
     N._check("lbm_step", st)
@@ -202,7 +213,7 @@ def moments(state: State, fields: bool = True, segments=None, stream=None,
     st, wsn = N.lbm_moments(params, n, lat.stride, lat.adj, state.f, rho, u, segments,
                             totals, query=True)
     N._check("lbm_moments", st)
-    ws = torch.empty(max(wsn, 1), dtype=torch.uint8, device=dev)
+    ws = _hold(torch.empty(max(wsn, 1), dtype=torch.uint8, device=dev), stream)
     st, _ = N.lbm_moments(params, n, lat.stride, lat.adj, state.f, rho, u, segments, totals,
                           ws, wsn, stream)
     N._check("lbm_moments", st)
@@ -230,7 +241,7 @@ def objective(state: State, segments=None, stream=None) -> torch.Tensor:
     st, wsn = N.lbm_objective(state.params, state.n, lat.stride, lat.adj, state.f, segments, J,
                               query=True)
     N._check("lbm_objective", st)
-    ws = torch.empty(max(wsn, 1), dtype=torch.uint8, device=lat.device)
+    ws = _hold(torch.empty(max(wsn, 1), dtype=torch.uint8, device=lat.device), stream)
     st, _ = N.lbm_objective(state.params, state.n, lat.stride, lat.adj, state.f, segments, J, ws,
                             wsn, stream)
     N._check("lbm_objective", st)
@@ -248,7 +259,7 @@ def partition_stats(lat: Lattice, n_chunks: int, n: int | None = None, stream=No
     iface = torch.empty(n_chunks, dtype=torch.int32, device=dev)
     st, wsn = N.lbm_partition_stats(n, lat.stride, lat.adj, n_chunks, remote, nb, iface, query=True)
     N._check("lbm_partition_stats", st)
-    ws = torch.empty(wsn, dtype=torch.uint8, device=dev)
+    ws = _hold(torch.empty(wsn, dtype=torch.uint8, device=dev), stream)
     st, _ = N.lbm_partition_stats(n, lat.stride, lat.adj, n_chunks, remote, nb, iface, ws, wsn,
                                   stream)
     N._check("lbm_partition_stats", st)
@@ -310,7 +321,7 @@ def _step_coded(state: State, comp: Compressed, codes8, n_steps, persistent, seg
         # lbm_step_batch: per-segment parameter sets and / or one persistent launch
         ws, wsn = _step_workspace(state, persistent, segments, lambda: N.lbm_step_batch(
             state.params, state.n, lat.stride, codes8, comp.codes, comp.tile_records, lat.adj,
-            state.ns, state.f, state.g, n_steps, 1, segments, query=True))
+            state.ns, state.f, state.g, n_steps, 1, segments, query=True), stream)
         st, _ = N.lbm_step_batch(state.params, state.n, lat.stride, codes8, comp.codes,
                                  comp.tile_records, lat.adj, state.ns, state.f, state.g, n_steps,
                                  int(persistent), segments, ws, wsn, stream)

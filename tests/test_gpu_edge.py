@@ -111,3 +111,34 @@ def test_all_cells_in_one_member_with_set_one():
     ref = L.init(lat, used)
     L.step(ref, 6)
     assert torch.equal(st.f[:, :n], ref.f[:, :n])
+
+
+def test_calls_on_a_side_stream():
+    """Steps with parameter sets, moments and the objective queued on a
+    stream other than torch's current one, while the current stream
+    allocates and writes memory (which would take over any workspace freed
+    too early): results equal the same calls on the current stream."""
+    geoms = [I.packing_boolean(92, 24, 24, 24, 2.0, 4.0, 0.5),
+             I.packing_boolean(93, 20, 20, 20, 2.0, 3.0, 0.45)]
+    batch = L.Batch([dev_flags(g) for g in geoms], [g.periodic for g in geoms], "lex",
+                    tile_align=True)
+    prms = [L.params(0.8, 3 / 16, (1e-5, 0, 0), "f64"), L.params(1.1, 3 / 16, (2e-5, 0, 0), "f64")]
+    segs = [(batch.bases[k], batch.counts[k], k) for k in range(2)]
+    print_case("side stream", batch.counts)
+    ref = L.init(batch.lattice, list(prms), n=batch.total, segments=segs)
+    L.step(ref, 6)
+    _, u_ref, tot_ref = L.moments(ref)
+    J_ref = L.objective(ref)
+    side = torch.cuda.Stream()
+    st = L.init(batch.lattice, list(prms), n=batch.total, segments=segs)
+    side.wait_stream(torch.cuda.current_stream())  # the state's init ran on the current stream
+    L.step(st, 6, stream=side)
+    _, u, tot = L.moments(st, stream=side)
+    J = L.objective(st, stream=side)
+    junk = [torch.full((1 << 20,), 7, dtype=torch.uint8, device="cuda") for _ in range(64)]
+    side.synchronize()
+    del junk
+    assert torch.equal(st.f[:, :batch.total], ref.f[:, :batch.total])
+    for b, c, _ in segs:  # fields are written in the members' columns only
+        assert torch.equal(u[:, b:b + c], u_ref[:, b:b + c])
+    assert torch.equal(tot, tot_ref) and torch.equal(J, J_ref)
