@@ -196,6 +196,8 @@ def step(state: State, n_steps: int = 1, persistent: bool = False, segments=None
 def moments(state: State, fields: bool = True, segments=None, stream=None,
             check_finite: bool = False):
     """(rho [n], u [3][n], totals [n_seg or 1][4]) in FP64 on the device.
+    With segments, rho and u are written in the segments' columns only (the
+    padding between tile-aligned batch members is left as allocated).
     check_finite: the library reads the totals back and raises LbmError
     (LBM_ENONFINITE) if one is NaN or infinite."""
     assert getattr(state, "phase", 0) == 0, "in-place state must be in phase 0 (an even step count)"
