@@ -14,7 +14,9 @@
  *  - The caller owns all memory.  The library never allocates device memory;
  *    calls that need scratch space take a caller-provided workspace whose
  *    size is obtained by calling with workspace == NULL (size query).
- *  - The library keeps no global state.  Every call is ordered on `stream`
+ *  - The library keeps no global state, with one exception: the fixed
+ *    per-device scratch array of lbm_moments_noalloc (see there).  Every call
+ *    is ordered on `stream`
  *    (a hipStream_t, NULL = the null stream) and asynchronous, except the
  *    outputs marked "synchronous" which are returned to the host.
  *  - Every call returns an lbm_status and never aborts or throws.  Argument
