@@ -15,10 +15,10 @@
  *    calls that need scratch space take a caller-provided workspace whose
  *    size is obtained by calling with workspace == NULL (size query).
  *  - The library keeps no global state, with one exception: the fixed
- *    per-device scratch array of lbm_moments_noalloc (see there).  Every call
- *    is ordered on `stream`
- *    (a hipStream_t, NULL = the null stream) and asynchronous, except the
- *    outputs marked "synchronous" which are returned to the host.
+ *    per-device scratch array of lbm_moments_noalloc (see there).
+ *  - Every call is ordered on `stream` (a hipStream_t, NULL = the null
+ *    stream) and asynchronous, except the outputs marked "synchronous" which
+ *    are returned to the host.
  *  - Every call returns an lbm_status and never aborts or throws.  Argument
  *    errors are detected on the host before any launch.  A launch failure
  *    reported by the HIP runtime returns LBM_EHIP; faults that surface later
