@@ -194,9 +194,10 @@ __device__ bool wait_at_least(unsigned int* cnt, unsigned int target, int* err) 
 // a pass of the walk covers a group of 4 consecutive tiles, one tile per
 // quarter of the waves, and every wave walks its own quarter-tiles without
 // waiting for the others; the waves of a workgroup meet only at the grid
-// barrier between steps.  16 independent waves per CU keep as many loads in
-// flight as the one-launch-per-step sweep does (4 waves per SIMD); a
-// 256-thread workgroup per CU (one wave per SIMD) left each tile's
+// barrier between steps.  16 independent waves per CU (4 per SIMD, the
+// occupancy of the FP64 one-launch-per-step sweep; the narrower storages
+// allow more, which measured no faster at 6 per SIMD) keep many loads in
+// flight; a 256-thread workgroup per CU (one wave per SIMD) left each tile's
 // dependent loads exposed and ran at about 60 % of the per-step rate.
 constexpr int kPThreads = 1024;
 constexpr int kPWaves = kPThreads / 64;
