@@ -206,6 +206,18 @@ def adjoint(a):
     T, k = 500, 22
     t_fwd, (J, ckpts, _) = timed(lambda: AD.forward_states(lat, prm, ns, T, k, comp))
     t_bwd, grad = timed(lambda: AD.adjoint_gradient(lat, prm, ns, T, k, ckpts, comp))
+    states_two_level = len(ckpts) + k  # checkpoints + the segment buffer
+    # binomial checkpointing: the same gradient with fewer states held
+    revolve = []
+    for snaps in (4, 10, 42):
+        stats = {}
+        t_rev, g_rev = timed(lambda: AD.adjoint_gradient_revolve(lat, prm, ns, T, snaps, comp,
+                                                                 stats=stats))
+        revolve.append({"snapshots": snaps, "states_held": stats["states_held"],
+                        "forward_sweeps": stats["forward_sweeps"],
+                        "backward_s": round(t_rev, 4),
+                        "bitwise_two_level": bool(torch.equal(g_rev, grad))})
+        del g_rev
     grad = grad.cpu().numpy()[:n]
     # adjoint kernel alone, over the 8-bit codes, the 16-bit codes and the full list
     narrow, escape = code_mix(comp)
@@ -294,6 +306,7 @@ def adjoint(a):
     emit({"experiment": "adjoint", "workload": f"pbb_box {n_edge}^3", "n_fluid": n, "steps": T,
           "checkpoint_every": k, "J_mean_ux": float(J), "forward_s": round(t_fwd, 4),
           "backward_s": round(t_bwd, 4), "backward_over_forward": round(t_bwd / t_fwd, 2),
+          "two_level_states_held": states_two_level, "revolve": revolve,
           "layout": [S, nt_best, chunk_best], "layout_table_us": table,
           "adjoint_step_us": round(t_adj * 1e6, 1), "adjoint_codes": "8-bit",
           "narrow_cells": round(narrow, 4), "escape_cells": round(escape, 4),

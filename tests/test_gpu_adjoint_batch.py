@@ -142,6 +142,36 @@ def test_gradient_vs_oracle_with_checkpoints(pbb):
     assert np.abs(grad_gpu - grad).max() <= 1e-12 * np.abs(grad).max()
 
 
+@pytest.mark.parametrize("snapshots", [0, 1, 3, 8, 30])
+def test_revolve_gradient_is_bitwise_two_level(pbb, snapshots):
+    """Binomial checkpointing with 0 to 30 snapshot slots delivers the same
+    states in the same order as two-level checkpointing, so the gradient is
+    bitwise the same; it runs exactly the schedule's optimal number of
+    forward sweeps."""
+    from paper_1111_1129_amd.checkpointing import revolve_closed_form
+    g, sp, lat, ns = pbb
+    prm = L.params(0.8, 3 / 16, (1e-5, 0, 0), "f64s")
+    T, k = 23, 5
+    print_case("revolve", snapshots, T)
+    nsd = torch.from_numpy(ns).cuda()
+    ref = AD.adjoint_gradient(lat, prm, nsd, T, k)
+    stats = {}
+    grad = AD.adjoint_gradient_revolve(lat, prm, nsd, T, snapshots, stats=stats)
+    assert torch.equal(grad, ref)
+    assert stats["forward_sweeps"] == revolve_closed_form(T, snapshots + 1)
+
+
+def test_permeability_autograd_revolve(pbb):
+    g, sp, lat, ns = pbb
+    prm = L.params(0.8, 3 / 16, (1e-5, 0, 0), "f64s")
+    nsd = torch.from_numpy(ns).cuda().requires_grad_(True)
+    J = AD.PermeabilityFn.apply(nsd, lat, prm, 12, 4, 2)  # 2 snapshot slots
+    J.backward()
+    _, grad = ogradient(prm, sp, ns, 12)
+    g = nsd.grad.cpu().numpy()[:sp.n_fluid]
+    assert np.abs(g - grad).max() <= 1e-12 * np.abs(grad).max()
+
+
 def test_permeability_autograd(pbb):
     g, sp, lat, ns = pbb
     prm = L.params(0.8, 3 / 16, (1e-5, 0, 0), "f64s")
