@@ -86,16 +86,19 @@ def test_zero_steps_and_empty_list_are_no_ops():
     lat = L.build(dev_flags(g), g.periodic, "lex")
     prm = L.params(0.8, 3 / 16, (1e-5, 0, 0), "f32")
     st = L.init(lat, prm)
-    before = st.f.clone()
+    n = lat.n_fluid
+    # the listed columns only: the padding up to the row stride is never
+    # written and may hold NaN bit patterns, which compare unequal
+    before = st.f[:, :n].clone()
     comp = L.narrow(L.compress(lat))
     L.step(st, 0, persistent=True)
     L.step_c8(st, comp, 0, persistent=True)
-    L.step(st, 0, segments=[(0, lat.n_fluid, 0)])
-    assert torch.equal(st.f, before)
+    L.step(st, 0, segments=[(0, n, 0)])
+    assert torch.equal(st.f[:, :n], before)
     # n = 0 with parameter sets: nothing is launched, nothing is read
     rc, _ = N.lbm_step([prm, prm], 0, lat.stride, lat.adj, None, st.f, st.g, 3, 0, None)
     assert rc == N.LBM_OK
-    assert torch.equal(st.f, before)
+    assert torch.equal(st.f[:, :n], before)
 
 
 def test_all_cells_in_one_member_with_set_one():
