@@ -188,12 +188,13 @@ lbm_status lbm_build_adjacency(const lbm_geom* g, const uint8_t* flag, int64_t b
  * shifted storage, computed as w_i [(rho0 - 1) + ...]) for list cells [0, n)
  * of every row.  The element type of f follows p->storage.  To initialise a
  * batch member, offset f by its base (in elements).
- *  p      (host) parameters (storage is used).
+ *  p      (host) parameters (only the storage is used; the other fields are
+ *         checked by the sweeps that use them).
  *  n, stride  cells written and row stride of f ([19][stride]).
  *  f      PDF array, written (caller-owned).
  *  rho0   density; u0 (host) 3 doubles, or NULL for u0 = 0.
  * Errors: LBM_EINVAL (NULL p/f, n < 0, stride < n, bad storage, non-finite
- * rho0), LBM_EOVERFLOW (19*stride >= 2^32), LBM_EHIP.
+ * rho0 or u0), LBM_EOVERFLOW (19*stride >= 2^32), LBM_EHIP.
  */
 lbm_status lbm_init(const lbm_params* p, int64_t n, int64_t stride, void* f, double rho0,
                     const double* u0, void* stream);

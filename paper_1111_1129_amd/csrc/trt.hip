@@ -124,6 +124,8 @@ using namespace lbm;
 extern "C" lbm_status lbm_init(const lbm_params* p, int64_t n, int64_t stride, void* f,
                                double rho0, const double* u0, void* stream) {
     if (!p || !f || !valid_storage(p->storage) || !std::isfinite(rho0)) return LBM_EINVAL;
+    if (u0 && !(std::isfinite(u0[0]) && std::isfinite(u0[1]) && std::isfinite(u0[2])))
+        return LBM_EINVAL;
     if (lbm_status st = check_layout(n, stride); st != LBM_OK) return st;
     hipStream_t s = as_stream(stream);
     switch (p->storage) {

@@ -433,3 +433,22 @@ def test_parameter_set_and_batch_argument_errors(lib):
     assert lib.lbm_objective(two, 2, 1000, 1024, d, d, None, 0, d, None, C.byref(tot),
                              None) == N.LBM_OK and tot.value > 0  # size query
 
+
+
+def test_init_argument_errors(lib):
+    """lbm_init refuses a non-finite density or initial velocity on the host."""
+    from paper_1111_1129_amd import _native as N
+    P = C.c_void_p
+    lib.lbm_init.restype = C.c_int32
+    lib.lbm_init.argtypes = [C.POINTER(N.lbm_params), C.c_int64, C.c_int64, P, C.c_double, P, P]
+    p = N.make_params(0.8, 3 / 16, (1e-6, 0, 0), "f64")
+    d = P(4096)
+    nan_u = (C.c_double * 3)(0.0, float("nan"), 0.0)
+    inf_u = (C.c_double * 3)(float("inf"), 0.0, 0.0)
+    assert lib.lbm_init(C.byref(p), 10, 10, d, float("nan"), None, None) == N.LBM_EINVAL
+    assert lib.lbm_init(C.byref(p), 10, 10, d, 1.0, C.cast(nan_u, P), None) == N.LBM_EINVAL
+    assert lib.lbm_init(C.byref(p), 10, 10, d, 1.0, C.cast(inf_u, P), None) == N.LBM_EINVAL
+    assert lib.lbm_init(C.byref(p), 10, 10, None, 1.0, None, None) == N.LBM_EINVAL
+    assert lib.lbm_init(C.byref(N.make_params(0.8, 3 / 16, storage=9)), 10, 10, d, 1.0, None,
+                        None) == N.LBM_EINVAL
+    assert lib.lbm_init(C.byref(p), 10, 9, d, 1.0, None, None) == N.LBM_EINVAL  # stride < n

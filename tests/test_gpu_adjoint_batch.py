@@ -129,6 +129,37 @@ def test_adjoint_over_codes_is_bitwise_the_adjoint(order):
             assert torch.equal(outs[0][0], lt) and torch.equal(outs[0][1], gr)
 
 
+@pytest.mark.parametrize("order", ["lex", "morton2", "random"])
+def test_adjoint_scatter_is_a_permutation(order):
+    """lambda^t starts as NaN in every slot; one adjoint step writes 19 values
+    per cell through the adjacency, so if every one of the 19 n listed slots
+    is finite afterwards, the 19 n writes hit 19 n distinct slots: each slot
+    exactly once.  For the full list, the 16-bit and the 8-bit codes."""
+    g = I.pbb_box(4, n=40)
+    print_case("adjoint scatter permutation", order, "pbb_box 40^3")
+    lat = L.build(dev_flags(g), g.periodic, order, 5 if order == "random" else 0)
+    n, S = lat.n_fluid, lat.stride
+    comp = L.narrow(L.compress(lat))
+    f = torch.from_numpy(random_state(n, 4, amp=1e-3, shifted=True, stride=S)).cuda()
+    lam = torch.zeros((19, S), dtype=torch.float64, device="cuda")
+    lam[:, :n] = torch.rand((19, n), dtype=torch.float64,
+                            generator=torch.Generator().manual_seed(7)).cuda()
+    prm = L.params(0.8, 3 / 16, (1e-5, 0, 0), "f64s")
+    for form in ("full", "c16", "c8"):
+        lt = torch.full((19, S), float("nan"), dtype=torch.float64, device="cuda")
+        if form == "c16":
+            rc = N.lbm_step_adjoint_c16(prm, n, S, comp.codes, comp.tile_records, lat.adj, f,
+                                        None, lam, lt, None)
+        elif form == "c8":
+            rc = N.lbm_step_adjoint_c8(prm, n, S, comp.codes8, comp.codes, comp.tile_records,
+                                       lat.adj, f, None, lam, lt, None)
+        else:
+            rc = N.lbm_step_adjoint(prm, n, S, lat.adj, f, None, lam, lt, None)
+        assert rc == 0
+        assert torch.isfinite(lt[:, :n]).all(), form
+        assert torch.isnan(lt[:, n:]).all(), form  # nothing outside the list
+
+
 def test_gradient_vs_oracle_with_checkpoints(pbb):
     g, sp, lat, ns = pbb
     prm = L.params(0.8, 3 / 16, (1e-5, 0, 0), "f64s")

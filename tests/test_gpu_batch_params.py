@@ -136,3 +136,27 @@ def test_nonfinite_totals_are_reported():
     assert e.value.status == N.LBM_ENONFINITE
     _, _, tot = L.moments(st, fields=False)  # without the flag: no check
     assert not torch.isfinite(tot).all()
+
+
+def test_nan_body_force_is_refused_or_reported():
+    """A body force of NaN (gx = NaN) never reaches a kernel: lbm_step
+    refuses it on the host (LBM_EINVAL), as lbm_init refuses a NaN initial
+    velocity (lbm_init reads only the storage of p).  A state that goes
+    non-finite anyway (a diverging run, modelled by an overflowing state
+    planted from the host) is reported by the checked moments."""
+    g = I.packing_small(1)
+    lat = L.build(dev_flags(g), g.periodic, "lex")
+    for storage in ("f64", "f32s", "f16s"):
+        ok = L.params(0.8, 3 / 16, (1e-6, 0, 0), storage)
+        bad = L.params(0.8, 3 / 16, (float("nan"), 0, 0), storage)
+        st = L.init(lat, ok)
+        rc, _ = N.lbm_step(bad, st.n, lat.stride, lat.adj, None, st.f, st.g, 2, 0, None)
+        assert rc == N.LBM_EINVAL, storage
+        assert N.lbm_init(ok, st.n, lat.stride, st.g, 1.0, (float("nan"), 0, 0)) == N.LBM_EINVAL
+        L.step(st, 2)
+        L.moments(st, fields=False, check_finite=True)  # finite: no error
+        st.f[3, :64] = float("inf")  # a blown-up corner of the state
+        L.step(st, 1)
+        with pytest.raises(N.LbmError) as e:
+            L.moments(st, fields=False, check_finite=True)
+        assert e.value.status == N.LBM_ENONFINITE, storage
