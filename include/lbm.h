@@ -410,6 +410,31 @@ lbm_status lbm_moments_noalloc(const lbm_params* p, int32_t n_params, int64_t n,
                                void* stream);
 
 /*
+ * lbm_check_adjacency -- checked mode of an adjacency list (a validation and
+ * debugging aid for adjacencies built or loaded outside the library).
+ *
+ * For the n list cells of one geometry at columns [base, base + n), with
+ * the entry contract of lbm_build_adjacency (Sec. 2: the adjacency list;
+ * Sec. 7: the pull scheme): every entry must lie in rows 1..18 of those
+ * columns (in particular below 19 * stride), and the 18 n entries must be a
+ * permutation of those 18 n slots, each referenced exactly once -- the
+ * property that makes the pull sweep read every population once and the
+ * adjoint and in-place scatters write every slot once.  The check never uses
+ * an out-of-range entry as an address.
+ *  base, n, stride, adj  the geometry's columns and the [18][stride] list.
+ *  result  (host, synchronous) int64 [2]: [0] entries out of range, [1] slots
+ *          of the 18 n not referenced exactly once (0 and 0: valid).
+ *  workspace, ws_bytes  scratch of 18 n + 64 uint32 (query with workspace
+ *          NULL).
+ * Errors: LBM_EINVAL (base < 0, n < 0, NULL ws_bytes / adj / result),
+ * LBM_EOVERFLOW (19*stride >= 2^32), LBM_EWORKSPACE, LBM_EHIP.  A list that
+ * fails the check is reported through result with LBM_OK.
+ */
+lbm_status lbm_check_adjacency(int64_t base, int64_t n, int64_t stride, const uint32_t* adj,
+                               int64_t* result, void* workspace, size_t* ws_bytes,
+                               void* stream);
+
+/*
  * lbm_partition_stats -- communication metrics of cutting the list into
  * n_chunks near-equal chunks (Sec. 2: a solver on N processes cuts the 1-D
  * list into N equal chunks, some smaller by one cell; Sec. 7 and Fig. 7:

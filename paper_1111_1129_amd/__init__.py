@@ -31,7 +31,7 @@ def __getattr__(name):
     if name in ("lbm_build_adjacency", "lbm_init", "lbm_step", "lbm_step_adjoint", "lbm_moments",
                 "lbm_partition_stats", "lbm_compress_adjacency", "lbm_step_c16",
                 "lbm_step_inplace", "lbm_step_adjoint_c16", "lbm_step_adjoint_c8",
-                "lbm_narrow_codes", "lbm_step_c8",
+                "lbm_narrow_codes", "lbm_step_c8", "lbm_check_adjacency",
                 "lbm_step_inplace_c8", "lbm_version",
                 "LbmError"):
         from . import _native

@@ -33,8 +33,8 @@ ENTRY_POINTS = ("lbm_build_adjacency", "lbm_init", "lbm_step", "lbm_step_batch",
                 "lbm_step_adjoint", "lbm_moments", "lbm_objective", "lbm_moments_noalloc",
                 "lbm_partition_stats", "lbm_compress_adjacency", "lbm_step_c16",
                 "lbm_step_inplace", "lbm_step_adjoint_c16", "lbm_step_adjoint_c8",
-                "lbm_narrow_codes", "lbm_step_c8", "lbm_step_inplace_c8", "lbm_version",
-                "lbm_status_string")
+                "lbm_narrow_codes", "lbm_step_c8", "lbm_step_inplace_c8", "lbm_check_adjacency",
+                "lbm_version", "lbm_status_string")
 
 
 class lbm_geom(C.Structure):
@@ -112,6 +112,9 @@ def load(path: str = LIB_PATH):
         lib.lbm_step_adjoint_c8.restype = I32
         lib.lbm_step_adjoint_c8.argtypes = [C.POINTER(lbm_params), I64, I64, P, P, P, P, P, P,
                                             P, P, P, P]
+        lib.lbm_check_adjacency.restype = I32
+        lib.lbm_check_adjacency.argtypes = [I64, I64, I64, P, C.POINTER(C.c_int64), P,
+                                            C.POINTER(SZ), P]
         lib.lbm_narrow_codes.restype = I32
         lib.lbm_narrow_codes.argtypes = [I64, I64, P, P, P, C.POINTER(C.c_int64), P,
                                          C.POINTER(SZ), P]
@@ -268,6 +271,18 @@ def lbm_objective(params, n, stride, adj, f, segments, J, workspace=None, ws_byt
                            _ptr(adj), _ptr(f), seg, n_seg, _ptr(J),
                            None if query else _ptr(workspace), C.byref(ws), _stream(stream))
     return st, ws.value
+
+
+def lbm_check_adjacency(base, n, stride, adj, workspace=None, ws_bytes=0, stream=None,
+                        query=False):
+    """Returns (status, (entries out of range, slots not referenced once), ws_bytes)."""
+    lib = load()
+    res = (C.c_int64 * 2)(0, 0)
+    ws = C.c_size_t(ws_bytes)
+    st = lib.lbm_check_adjacency(base, n, stride, _ptr(adj), res,
+                                 None if query else _ptr(workspace), C.byref(ws),
+                                 None if query else _stream(stream))
+    return st, (int(res[0]), int(res[1])), ws.value
 
 
 def lbm_partition_stats(n, stride, adj, n_chunks, remote_links, neighbours, interface_cells,

@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB_PATH = os.path.join(PKG, "liblbm.so")
 SOURCES = ["assembly.hip", "trt.hip", "batch.hip", "moments.hip", "adjoint.hip",
-           "partition.hip", "compress.hip", "inplace.hip", "abi.cpp"]
+           "partition.hip", "compress.hip", "inplace.hip", "check.hip", "abi.cpp"]
 ARCH = "gfx950"
 
 

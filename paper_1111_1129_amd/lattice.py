@@ -250,6 +250,18 @@ def objective(state: State, segments=None, stream=None) -> torch.Tensor:
     return J
 
 
+def check_adjacency(lat: Lattice, stream=None) -> tuple[int, int]:
+    """(entries out of range, slots not referenced exactly once) of the
+    lattice's own columns (lbm_check_adjacency; (0, 0) for a valid list)."""
+    st, _, wsn = N.lbm_check_adjacency(lat.base, lat.n_fluid, lat.stride, lat.adj, query=True)
+    N._check("lbm_check_adjacency", st)
+    ws = torch.empty(wsn, dtype=torch.uint8, device=lat.device)
+    st, res, _ = N.lbm_check_adjacency(lat.base, lat.n_fluid, lat.stride, lat.adj, ws, wsn,
+                                       stream)
+    N._check("lbm_check_adjacency", st)
+    return res
+
+
 def partition_stats(lat: Lattice, n_chunks: int, n: int | None = None, stream=None):
     """(remote_links int64[G], neighbours int32[G], interface_cells int32[G])
     of cutting the list [0, n) into n_chunks near-equal chunks (paper Sec. 2,

@@ -452,3 +452,30 @@ def test_init_argument_errors(lib):
     assert lib.lbm_init(C.byref(N.make_params(0.8, 3 / 16, storage=9)), 10, 10, d, 1.0, None,
                         None) == N.LBM_EINVAL
     assert lib.lbm_init(C.byref(p), 10, 9, d, 1.0, None, None) == N.LBM_EINVAL  # stride < n
+
+
+def test_check_adjacency_arguments_and_query(lib):
+    from paper_1111_1129_amd import _native as N
+    P = C.c_void_p
+    res = (C.c_int64 * 2)(7, 7)
+    ws = C.c_size_t(0)
+    lib.lbm_check_adjacency.restype = C.c_int32
+    lib.lbm_check_adjacency.argtypes = [C.c_int64, C.c_int64, C.c_int64, P,
+                                        C.POINTER(C.c_int64), P, C.POINTER(C.c_size_t), P]
+    assert lib.lbm_check_adjacency(0, 1000, 1024, None, res, None, C.byref(ws), None) == N.LBM_OK
+    assert ws.value >= 18 * 1000 * 4 + 16  # the slot counts and two counters
+    assert lib.lbm_check_adjacency(-1, 10, 10, None, res, None, C.byref(ws), None) == N.LBM_EINVAL
+    assert lib.lbm_check_adjacency(0, -1, 10, None, res, None, C.byref(ws), None) == N.LBM_EINVAL
+    assert lib.lbm_check_adjacency(8, 10, 10, None, res, None, C.byref(ws), None) == N.LBM_EINVAL
+    assert lib.lbm_check_adjacency(0, 10, (1 << 32) // 19 + 1, None, res, None, C.byref(ws),
+                                   None) == N.LBM_EOVERFLOW
+    assert lib.lbm_check_adjacency(0, 10, 10, None, res, None, None, None) == N.LBM_EINVAL
+    big = C.c_size_t(1 << 20)
+    assert lib.lbm_check_adjacency(0, 10, 10, None, res, P(4096), C.byref(big),
+                                   None) == N.LBM_EINVAL          # NULL adj
+    small = C.c_size_t(8)
+    assert lib.lbm_check_adjacency(0, 10, 10, P(4096), res, P(4096), C.byref(small),
+                                   None) == N.LBM_EWORKSPACE
+    # an empty list needs no launch: valid, nothing counted
+    assert lib.lbm_check_adjacency(0, 0, 0, P(4096), res, P(4096), C.byref(big), None) == N.LBM_OK
+    assert (res[0], res[1]) == (0, 0)

@@ -140,3 +140,37 @@ def test_partition_stats_tube_3072_chunks(tube):
     np.testing.assert_array_equal(r.cpu().numpy(), orr)
     np.testing.assert_array_equal(nb.cpu().numpy(), onb)
     np.testing.assert_array_equal(ifc.cpu().numpy(), oifc)
+
+
+@pytest.mark.parametrize("order,param", ORDERS)
+def test_checked_mode_accepts_the_assembled_lists(order, param):
+    """lbm_check_adjacency: every list the assembly builds has all entries in
+    range and references each of its 18 n slots exactly once."""
+    g = I.packing_small(1)
+    print_case("check adjacency", order, param)
+    lat = L.build(dev_flags(g), g.periodic, order, param)
+    assert L.check_adjacency(lat) == (0, 0)
+
+
+def test_checked_mode_on_batch_members_and_corrupted_lists():
+    geoms = [I.packing_boolean(60 + k, 20 + 3 * k, 20, 20, 2.0, 4.0, 0.5) for k in range(3)]
+    batch = L.Batch([dev_flags(g) for g in geoms], [g.periodic for g in geoms], "morton2",
+                    tile_align=True)
+    print_case("check adjacency batch", batch.counts)
+    for lat in batch.lattices:
+        assert L.check_adjacency(lat) == (0, 0)
+    lat = batch.lattices[1]
+    b, n, S = lat.base, lat.n_fluid, lat.stride
+    good = lat.adj.clone()
+    # one entry duplicated: one slot referenced twice, another never
+    lat.adj[3, b + 100] = lat.adj[3, b + 101]
+    assert L.check_adjacency(lat) == (0, 2)
+    lat.adj.copy_(good)
+    # an entry in row 0 (the implicit rest slot), one past 19 * stride, one in
+    # another member's columns: each out of range and its slot left unreferenced
+    lat.adj[0, b + 5] = b + 5
+    lat.adj[7, b + 9] = -16  # the uint32 entry 0xFFFFFFF0, far past 19 * stride
+    lat.adj[2, b + 11] = 3 * S + batch.bases[2]
+    assert L.check_adjacency(lat) == (3, 3)
+    lat.adj.copy_(good)
+    assert L.check_adjacency(lat) == (0, 0)
