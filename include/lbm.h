@@ -259,6 +259,12 @@ lbm_status lbm_step(const lbm_params* p, int32_t n_params, const lbm_segment* se
  *  codes, tile_records  from lbm_compress_adjacency for the same n, stride and
  *           adj, or both NULL (full list; codes8 must then be NULL too).
  *  The other arguments as lbm_step.
+ * With persistent = 0 the call only enqueues kernel launches on `stream` (no
+ * allocation, memset, copy or synchronisation), so a caller may capture it in
+ * a HIP graph with the workspace allocated beforehand: one graph launch then
+ * runs all n_steps sweeps, each with the hardware's workgroup dispatch, and
+ * gives the per-step launches' results bit for bit.  The persistent launch
+ * synchronises the stream to report LBM_EBARRIER and cannot be captured.
  * Errors: as lbm_step, and LBM_EINVAL for codes8 without codes or only one of
  * codes and tile_records.
  */
