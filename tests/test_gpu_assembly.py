@@ -115,6 +115,8 @@ def test_tube_full_size(tube, order, param):
     counts = np.bincount(dense.ravel(), minlength=19 * n)
     assert counts.shape == (19 * n,)
     assert (counts[:n] == 0).all() and (counts[n:] == 1).all()
+    # the library's checked mode reaches the same verdict on the device
+    assert L.check_adjacency(lat) == (0, 0)
 
 
 @pytest.mark.parametrize("order,param", [("lex", 0), ("blocked", 8), ("hilbert", 0)])
